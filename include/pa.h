@@ -1,0 +1,177 @@
+/*
+ * libpa — Toeplitz-hash privacy amplification on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper section 2.1, Eq. 1; section 2.3, steps 1-2; section 3,
+ * Fig. 1-2, Eq. 4-6): for an n-bit key x and an (n+m-1)-bit seed s, the m x n
+ * Toeplitz matrix over GF(2) has T[i][j] = s[i - j + n - 1], and the hash is
+ *
+ *     y_i = XOR_{j<n} ( s[i - j + n - 1] AND x_j ),   0 <= i < m.
+ *
+ * y is the window [n-1, n+m-1) of the polynomial product s(z) x(z) reduced mod
+ * 2 (section 3, step 3: outputs n .. n+m-1 of the product, counted from 1;
+ * Eq. 6: mod-2 addition).  The library evaluates it as an exact FFT convolution
+ * (integer rounding, parity, output window), splitting long keys into chunks
+ * and long outputs into windows whose partial hashes are XOR-merged (Eq. 4-6).
+ *
+ * Bit strings: arrays of uint64_t words, LSB-first: bit k of a string is
+ * (w[k >> 6] >> (k & 63)) & 1.  A k-bit string occupies ceil(k/64) words.
+ * Bits beyond n (key) or n+m-1 (seed) in the last word are ignored.  Output
+ * bits beyond m in the last word are written as 0.
+ *
+ * Memory: unless PA_DEVICE_PTRS is given, seed/key/out are host pointers and
+ * the call copies them (and the call is synchronous).  With PA_DEVICE_PTRS they
+ * are device pointers on the context's device (e.g. a torch tensor's
+ * data_ptr()).  The caller owns seed, key and out and keeps them alive until the
+ * call has completed; out must not overlap seed or key.  The library owns its
+ * workspace, plans, twiddle tables, tuning data and copies of registered
+ * seeds.
+ *
+ * Errors: every entry point returns a pa_status; nothing is thrown across the
+ * ABI.  A context is used by one host thread at a time (calls on one context
+ * are serialised by an internal mutex).
+ */
+#ifndef PA_H
+#define PA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PA_OK = 0,
+    PA_EINVAL = 1,       /* n == 0, m == 0, NULL pointer, bad flags, unknown id */
+    PA_ENOMEM = 2,       /* the job cannot fit the HBM budget even when tiled    */
+    PA_EDEVICE = 3,      /* a HIP runtime error (no device, launch failure, ...) */
+    PA_EPRECISION = 4,   /* a floating-point certificate failed, fallback off    */
+    PA_EBUSY = 5,        /* serving queue full                                   */
+    PA_ENOTREADY = 6     /* ticket not finished (pa_poll)                         */
+} pa_status;
+
+/* ---- flags ---------------------------------------------------------------- */
+#define PA_DEVICE_PTRS    0x0001u  /* seed/key/out are device pointers                 */
+#define PA_PREC_AUTO      0x0000u  /* fastest certified plan (FP32 tiles + FP64 fallback) */
+#define PA_PREC_FP32_SEG  0x0010u  /* FP32 FFT tiles sized by the rounding bound        */
+#define PA_PREC_FP64      0x0020u  /* FP64 FFT, one tile where it fits ("plain" path)   */
+#define PA_PREC_NTT       0x0030u  /* exact number-theoretic transform mod 15*2^27+1    */
+#define PA_PREC_MASK      0x00F0u
+#define PA_NO_FALLBACK    0x0100u  /* report PA_EPRECISION instead of re-running FP64   */
+#define PA_ASYNC          0x0200u  /* with PA_DEVICE_PTRS and an exact or a-priori
+                                      certified plan (FP64, NTT): return once enqueued  */
+#define PA_TIMING         0x0400u  /* record per-kernel durations (pa_last_stats)       */
+
+typedef struct pa_ctx pa_ctx;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * workspace (0 = 8 GiB).  hip_stream: a hipStream_t to run on, or NULL for a
+ * stream owned by the context.  Returns PA_EDEVICE when no usable device. */
+pa_status pa_create(pa_ctx** ctx, int device, uint64_t hbm_budget_bytes, void* hip_stream);
+
+/* Destroy a context (waits for its work, frees its memory).  NULL is a no-op. */
+void pa_destroy(pa_ctx* ctx);
+
+/* y = T(seed) * key over GF(2), m output bits (see top of file).
+ * seed: n+m-1 bits; key: n bits; out: m bits (ceil(m/64) words, written).
+ * Synchronous unless PA_ASYNC applies.  PA_EINVAL for n == 0, m == 0, NULL
+ * pointers or an unknown precision; PA_ENOMEM when even the smallest tiling
+ * exceeds the budget; PA_EPRECISION when a certificate fails and
+ * PA_NO_FALLBACK is set. */
+pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m,
+                  const uint64_t* key, uint64_t* out, uint32_t flags);
+
+/* One job of a batch. */
+typedef struct {
+    const uint64_t* seed;   /* n+m-1 bits */
+    const uint64_t* key;    /* n bits     */
+    uint64_t* out;          /* m bits     */
+    uint64_t n, m;
+} pa_job;
+
+/* Hash `count` independent jobs (uneven n and m) with one launch per pipeline
+ * pass for all their tiles; tile and segment sizes come from the tuner.
+ * per_job (optional, count entries) receives each job's status; the return
+ * value is PA_OK only if every job succeeded.  Pointer kind per PA_DEVICE_PTRS
+ * as for pa_hash.  Synchronous. */
+pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs, uint64_t count, uint32_t flags,
+                        pa_status* per_job);
+
+/* ---- serving (continuous batching) --------------------------------------- */
+
+/* Copy a seed of nbits bits (device pointer if PA_DEVICE_PTRS in flags, else
+ * host) into library-owned device memory and return its id.  Requests that
+ * name the id use its first n+m-1 bits. */
+pa_status pa_seed_register(pa_ctx* ctx, const uint64_t* seed, uint64_t nbits, uint32_t flags,
+                           uint32_t* seed_id);
+
+/* Queue a hash request against a registered seed.  key (n bits) and out (m
+ * bits) are device pointers that stay valid until the ticket completes.
+ * Requests are admitted to the device as the HBM budget allows and are
+ * batched with whatever else is waiting; a request that arrives while others
+ * run joins the next launch.  PA_EBUSY when the queue is full, PA_EINVAL when
+ * n+m-1 exceeds the seed. */
+pa_status pa_submit(pa_ctx* ctx, uint32_t seed_id, uint64_t n, uint64_t m,
+                    const uint64_t* key, uint64_t* out, uint64_t* ticket);
+
+/* done = 1 when the ticket's output is complete, else 0. */
+pa_status pa_poll(pa_ctx* ctx, uint64_t ticket, int* done);
+
+/* Block until the ticket completes; returns the request's status. */
+pa_status pa_wait(pa_ctx* ctx, uint64_t ticket);
+
+/* Latency of a finished ticket in seconds (submit -> completion seen). */
+pa_status pa_ticket_latency(pa_ctx* ctx, uint64_t ticket, double* seconds);
+
+/* ---- statistics ----------------------------------------------------------- */
+
+typedef struct {
+    uint32_t prec;            /* PA_PREC_* of the plan that ran               */
+    uint32_t log2_len;        /* FFT length L = 2^log2_len                    */
+    uint32_t n1, n2;          /* L = n1 * n2 (row and column lengths)         */
+    uint64_t chunk_bits;      /* key bits per tile (Bi)                       */
+    uint64_t window_bits;     /* output bits per tile (Bo)                    */
+    uint64_t tiles;           /* tiles run                                    */
+    uint64_t fallback_tiles;  /* tiles re-run in FP64 after a failed check    */
+    double max_residual;      /* max |z - rint z| over all outputs            */
+    double max_abs;           /* max |z| over all outputs                     */
+    double bound;             /* predicted max error of the plan              */
+    double ms_pass[4];        /* PA_TIMING: summed kernel ms of pass 1,2,3, merge */
+    uint64_t model_bytes;     /* algorithmic HBM bytes of the FFT passes      */
+    uint64_t launches;        /* kernel launches                              */
+} pa_stats;
+
+/* Statistics of the last pa_hash / pa_hash_batch on this context. */
+pa_status pa_last_stats(pa_ctx* ctx, pa_stats* stats);
+
+/* Human-readable name of a status. */
+const char* pa_strerror(pa_status status);
+
+/* ---- host-only planning (no device needed) --------------------------------- */
+
+typedef struct {
+    uint32_t prec;        /* PA_PREC_FP32_SEG or PA_PREC_FP64 (or NTT)  */
+    uint32_t log2_len;    /* L = 2^log2_len                              */
+    uint32_t n1, n2;
+    uint64_t chunk_bits;  /* Bi: key bits per chunk (last chunk may be shorter) */
+    uint64_t window_bits; /* Bo: output bits per window, multiple of 64 unless it is m */
+    uint64_t chunks;      /* ceil(n / Bi) */
+    uint64_t windows;     /* ceil(m / Bo) */
+    double bound;         /* predicted max error (probabilistic model)  */
+    double cost;          /* model cost used to choose the plan          */
+} pa_plan;
+
+/* The plan pa_hash would use for (n, m) under the precision bits of flags,
+ * with the built-in cost model (no tuning data, no device).  Tile k (chunk b =
+ * k / windows, window o = k % windows) covers key bits [max(0, n-(b+1)Bi),
+ * n-b*Bi) and outputs [o*Bo, min(m, (o+1)*Bo)). */
+pa_status pa_plan_query(uint64_t n, uint64_t m, uint32_t flags, pa_plan* plan);
+
+/* Predicted max rounding error of one FP tile (probabilistic model with the
+ * calibration constant in use), for chunk Bi and FFT length 2^log2_len. */
+double pa_error_model(uint32_t prec, uint32_t log2_len, uint64_t chunk_bits);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PA_H */

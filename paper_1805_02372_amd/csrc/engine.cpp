@@ -1,0 +1,620 @@
+// libpa host engine: contexts, workspace, twiddle tables, plan execution with
+// per-tile certificates and FP64 fallback, and the C ABI of include/pa.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "pa.h"
+#include "pa_internal.hpp"
+#include "planner.hpp"
+#include "tables.hpp"
+#include "engine.hpp"
+
+using namespace pa;
+
+namespace pa {
+
+const char* status_name(pa_status s) {
+    switch (s) {
+        case PA_OK: return "PA_OK";
+        case PA_EINVAL: return "PA_EINVAL: invalid argument";
+        case PA_ENOMEM: return "PA_ENOMEM: does not fit the HBM budget";
+        case PA_EDEVICE: return "PA_EDEVICE: HIP runtime error";
+        case PA_EPRECISION: return "PA_EPRECISION: floating-point certificate failed";
+        case PA_EBUSY: return "PA_EBUSY: queue full";
+        case PA_ENOTREADY: return "PA_ENOTREADY: not finished";
+    }
+    return "unknown pa_status";
+}
+
+static uint64_t words_of(uint64_t bits) { return (bits + 63) >> 6; }
+
+// ------------------------------------------------------------ device memory
+
+pa_status DevBuf::ensure(Ctx* c, size_t need) {
+    if (need <= bytes) return PA_OK;
+    release(c);
+    size_t want = std::max(need, (size_t)256);
+    if (c->used.load() + want > c->budget) return PA_ENOMEM;
+    if (hipMalloc(&ptr, want) != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        return PA_ENOMEM;
+    }
+    bytes = want;
+    c->used += want;
+    return PA_OK;
+}
+
+void DevBuf::release(Ctx* c) {
+    if (ptr) {
+        (void)hipDeviceSynchronize();  // no launch may still use it
+        (void)hipFree(ptr);
+        c->used -= bytes;
+    }
+    ptr = nullptr;
+    bytes = 0;
+}
+
+pa_status HostBuf::ensure(size_t need) {
+    if (need <= bytes) return PA_OK;
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+    if (hipHostMalloc(&ptr, std::max(need, (size_t)256), hipHostMallocDefault) != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        return PA_ENOMEM;
+    }
+    bytes = std::max(need, (size_t)256);
+    return PA_OK;
+}
+
+void HostBuf::release() {
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+// ------------------------------------------------------------ twiddle tables
+
+pa_status Ctx::tables(int prec, int logL, Tables* out) {
+    std::lock_guard<std::mutex> lk(tab_mu);
+    const int key = prec * 100 + logL;
+    auto it = tabs.find(key);
+    if (it == tabs.end()) {
+        ClassGeom g;
+        if (!class_geometry(prec, logL, &g)) return PA_EINVAL;
+        DevTables dt;
+        size_t elt = prec == PREC_FP32 ? sizeof(float) : sizeof(double);
+        std::vector<unsigned char> host;
+        size_t ntw, nfa, nfb;
+        if (prec == PREC_FP32) {
+            TableHost<float> th;
+            build_tables<float>(logL, g.n1, g.n2, &th);
+            ntw = th.tw.size(); nfa = th.fa.size(); nfb = th.fb.size();
+            host.resize((ntw + nfa + nfb) * elt);
+            memcpy(host.data(), th.tw.data(), ntw * elt);
+            memcpy(host.data() + ntw * elt, th.fa.data(), nfa * elt);
+            memcpy(host.data() + (ntw + nfa) * elt, th.fb.data(), nfb * elt);
+            dt.t.fshift = th.fshift;
+        } else {
+            TableHost<double> th;
+            build_tables<double>(logL, g.n1, g.n2, &th);
+            ntw = th.tw.size(); nfa = th.fa.size(); nfb = th.fb.size();
+            host.resize((ntw + nfa + nfb) * elt);
+            memcpy(host.data(), th.tw.data(), ntw * elt);
+            memcpy(host.data() + ntw * elt, th.fa.data(), nfa * elt);
+            memcpy(host.data() + (ntw + nfa) * elt, th.fb.data(), nfb * elt);
+            dt.t.fshift = th.fshift;
+        }
+        pa_status st = dt.buf.ensure(this, host.size());
+        if (st != PA_OK) return st;
+        if (hipMemcpy(dt.buf.ptr, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return PA_EDEVICE;
+        unsigned char* base = (unsigned char*)dt.buf.ptr;
+        dt.t.tw = base;
+        dt.t.fa = base + ntw * elt;
+        dt.t.fb = base + (ntw + nfa) * elt;
+        it = tabs.emplace(key, dt).first;
+    }
+    *out = it->second.t;
+    return PA_OK;
+}
+
+// ------------------------------------------------------------ pass timing
+
+hipEvent_t PassTimer::mark(hipStream_t s) {
+    if (used == pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        pool.push_back(e);
+    }
+    hipEvent_t e = pool[used++];
+    (void)hipEventRecord(e, s);
+    return e;
+}
+
+void PassTimer::collect(double ms[4]) {
+    for (auto& sp : spans) {
+        float v = 0;
+        if (sp.second.first && sp.second.second &&
+            hipEventElapsedTime(&v, sp.second.first, sp.second.second) == hipSuccess)
+            ms[sp.first] += v;
+    }
+    reset();
+}
+
+void PassTimer::destroy() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+    reset();
+}
+
+// ------------------------------------------------------------ plan execution
+
+void fill_job(JobDesc* jd, const uint64_t* seed, const uint64_t* key, uint64_t* out, uint64_t n, uint64_t m,
+              const TilePlan& p) {
+    memset(jd, 0, sizeof(*jd));
+    jd->key = key;
+    jd->seed = seed;
+    jd->out = out;
+    jd->n = n;
+    jd->m = m;
+    jd->Bi = p.Bi;
+    jd->Bo = p.Bo;
+    jd->nchunks = (uint32_t)p.nchunks;
+    jd->nouts = (uint32_t)p.nouts;
+    jd->out_words = (uint32_t)words_of(m);
+}
+
+void Lane::release(Ctx* c) {
+    if (stream) (void)hipStreamSynchronize(stream);
+    ws.release(c);
+    part.release(c);
+    meta.release(c);
+    jobs_dev.release(c);
+    stage.release(c);
+    io.release(c);
+    meta_host.release();
+    jobs_host.release();
+    timer.destroy();
+    if (done) (void)hipEventDestroy(done);
+    done = nullptr;
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+    stream = nullptr;
+}
+
+// Tiles [first, end) through the three passes, G tiles per launch.
+static pa_status run_passes(const ClassKernels* K, JobTable jt, uint32_t first, uint32_t end, size_t G, Lane* ln,
+                            const Tables& tb, bool timing, uint64_t* launches) {
+    for (uint32_t t0 = first; t0 < end; t0 += (uint32_t)G) {
+        jt.tile0 = t0;
+        jt.ntiles = (uint32_t)std::min<size_t>(G, end - t0);
+        const launch_fn fns[3] = {K->pass1, K->pass2, K->pass3};
+        for (int p = 0; p < 3; ++p) {
+            hipEvent_t a = timing ? ln->timer.mark(ln->stream) : nullptr;
+            if (fns[p](jt, ln->ws.ptr, (uint32_t*)ln->part.ptr, (TileMeta*)ln->meta.ptr, tb, ln->stream))
+                return PA_EDEVICE;
+            if (timing) ln->timer.spans.push_back({p, {a, ln->timer.mark(ln->stream)}});
+        }
+        *launches += 3;
+    }
+    return PA_OK;
+}
+
+pa_status Lane::launch(Ctx* c, int prec_, int logL_, std::vector<JobDesc>& js, bool timing, bool fetch_meta,
+                       pa_stats* stats) {
+    const ClassKernels* K = class_kernels(prec_, logL_);
+    if (!K || js.empty()) return PA_EINVAL;
+    prec = prec_;
+    logL = logL_;
+    const ClassCfg& cfg = K->cfg;
+    uint32_t total = 0;
+    uint64_t stage_words = 0, max_words = 0;
+    for (JobDesc& jd : js) {
+        jd.tile_begin = total;
+        total += jd.nchunks * jd.nouts;
+        if (jd.nchunks > 1) {
+            stage_words += (uint64_t)jd.nchunks * jd.out_words;
+            max_words = std::max<uint64_t>(max_words, jd.out_words);
+        }
+    }
+    pa_status st = stage.ensure(c, std::max<uint64_t>(stage_words, 1) * 8);
+    if (st != PA_OK) return st;
+    uint64_t off = 0;
+    for (JobDesc& jd : js)
+        if (jd.nchunks > 1) {
+            jd.stage = (uint64_t*)stage.ptr + off;
+            off += (uint64_t)jd.nchunks * jd.out_words;
+        } else {
+            jd.stage = nullptr;
+        }
+    Tables tb;
+    st = c->tables(prec, logL, &tb);
+    if (st != PA_OK) return st;
+    st = meta.ensure(c, (size_t)total * sizeof(TileMeta));
+    if (st != PA_OK) return st;
+
+    // tiles per launch: as many as the budget allows, at least one
+    const size_t elt = cfg.prec == 32 ? 8 : 16;
+    const size_t tile_bytes = ((size_t)1 << cfg.logL) * elt;
+    const size_t part_bytes = (size_t)(cfg.n1 / cfg.b1) * sizeof(uint32_t);
+    size_t G = total;
+    if (ws.bytes < G * tile_bytes || part.bytes < G * part_bytes) {
+        const uint64_t u = c->used.load();
+        const uint64_t mine = ws.bytes + part.bytes;
+        const uint64_t avail = c->budget > u ? c->budget - u + mine : mine;
+        G = std::max<size_t>(1, std::min<size_t>(G, avail / (tile_bytes + part_bytes)));
+    }
+    st = ws.ensure(c, G * tile_bytes);
+    if (st != PA_OK) return st;
+    st = part.ensure(c, G * part_bytes);
+    if (st != PA_OK) return st;
+
+    JobTable jt{};
+    if (js.size() == 1) {
+        jt.one = js[0];
+        jt.njobs = 0;
+    } else {
+        st = jobs_dev.ensure(c, js.size() * sizeof(JobDesc));
+        if (st != PA_OK) return st;
+        st = jobs_host.ensure(js.size() * sizeof(JobDesc));
+        if (st != PA_OK) return st;
+        memcpy(jobs_host.ptr, js.data(), js.size() * sizeof(JobDesc));
+        if (hipMemcpyAsync(jobs_dev.ptr, jobs_host.ptr, js.size() * sizeof(JobDesc), hipMemcpyHostToDevice,
+                           stream) != hipSuccess)
+            return PA_EDEVICE;
+        jt.many = (const JobDesc*)jobs_dev.ptr;
+        jt.njobs = (uint32_t)js.size();
+    }
+    if (timing) timer.reset();
+    st = run_passes(K, jt, 0, total, G, this, tb, timing, &stats->launches);
+    if (st != PA_OK) return st;
+    if (max_words) {
+        jt.tile0 = 0;
+        jt.ntiles = total;
+        hipEvent_t a = timing ? timer.mark(stream) : nullptr;
+        if (launch_merge(jt, max_words, stream)) return PA_EDEVICE;
+        if (timing) timer.spans.push_back({3, {a, timer.mark(stream)}});
+        stats->launches += 1;
+    }
+    if (fetch_meta) {
+        st = meta_host.ensure((size_t)total * sizeof(TileMeta));
+        if (st != PA_OK) return st;
+        if (hipMemcpyAsync(meta_host.ptr, meta.ptr, (size_t)total * sizeof(TileMeta), hipMemcpyDeviceToHost,
+                           stream) != hipSuccess)
+            return PA_EDEVICE;
+    }
+    if (!done && hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) return PA_EDEVICE;
+    if (hipEventRecord(done, stream) != hipSuccess) return PA_EDEVICE;
+    jobs = js;
+    total_tiles = total;
+    stats->tiles += total;
+    return PA_OK;
+}
+
+static bool tile_ok(int prec, const TileMeta& mt, double* res, double* mabs) {
+    float r, a;
+    memcpy(&r, &mt.maxres, 4);
+    memcpy(&a, &mt.maxabs, 4);
+    *res = r;
+    *mabs = a;
+    const double abs_limit = prec == PREC_FP32 ? 1048576.0 : 1099511627776.0;   // 2^20, 2^40
+    return std::isfinite(r) && std::isfinite(a) && r <= 0.125f && a < abs_limit && mt.badpar == 0;
+}
+
+pa_status Lane::finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_status>* per_job) {
+    if (hipEventSynchronize(done) != hipSuccess) return PA_EDEVICE;
+    if (flags & PA_TIMING) timer.collect(stats->ms_pass);
+    const uint32_t total = total_tiles;
+    const TileMeta* mt = (const TileMeta*)meta_host.ptr;
+    std::vector<uint32_t> failed;
+    for (uint32_t t = 0; t < total; ++t) {
+        double r, a;
+        const bool ok = tile_ok(prec, mt[t], &r, &a);
+        stats->max_residual = std::max(stats->max_residual, r);
+        stats->max_abs = std::max(stats->max_abs, a);
+        if (!ok) failed.push_back(t);
+    }
+    if (failed.empty()) return PA_OK;
+    auto job_of = [&](uint32_t t) {
+        size_t lo = 0, hi = jobs.size() - 1;
+        while (lo < hi) {
+            size_t mid = (lo + hi + 1) / 2;
+            if (jobs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    };
+    const ClassKernels* K64 = class_kernels(PREC_FP64, logL);
+    if (prec != PREC_FP32 || (flags & PA_NO_FALLBACK) || !K64) {
+        if (per_job)
+            for (uint32_t t : failed) (*per_job)[job_of(t)] = PA_EPRECISION;
+        return PA_EPRECISION;
+    }
+    // Re-run each failed tile in FP64 (same geometry and length class) into
+    // the same output words, then re-merge its job.
+    Tables tb;
+    pa_status st = c->tables(PREC_FP64, logL, &tb);
+    if (st != PA_OK) return st;
+    st = ws.ensure(c, ((size_t)1 << logL) * 16);
+    if (st != PA_OK) return st;
+    st = part.ensure(c, (size_t)(K64->cfg.n1 / K64->cfg.b1) * sizeof(uint32_t));
+    if (st != PA_OK) return st;
+    std::vector<uint8_t> remerge(jobs.size(), 0);
+    pa_status result = PA_OK;
+    for (uint32_t t : failed) {
+        const size_t jx = job_of(t);
+        const uint32_t local = t - jobs[jx].tile_begin;
+        JobTable jt{};
+        jt.one = jobs[jx];
+        jt.one.tile_begin = 0;
+        jt.njobs = 0;
+        st = meta.ensure(c, (size_t)(local + 1) * sizeof(TileMeta));
+        if (st != PA_OK) return st;
+        st = run_passes(K64, jt, local, local + 1, 1, this, tb, false, &stats->launches);
+        if (st != PA_OK) return st;
+        stats->fallback_tiles += 1;
+        stats->tiles += 1;
+        TileMeta m64;
+        if (hipMemcpyAsync(&m64, (TileMeta*)meta.ptr + local, sizeof(TileMeta), hipMemcpyDeviceToHost, stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return PA_EDEVICE;
+        double r, a;
+        if (!tile_ok(PREC_FP64, m64, &r, &a)) {
+            result = PA_EPRECISION;
+            if (per_job) (*per_job)[jx] = PA_EPRECISION;
+        }
+        if (jobs[jx].nchunks > 1) remerge[jx] = 1;
+    }
+    for (size_t jx = 0; jx < jobs.size(); ++jx)
+        if (remerge[jx]) {
+            JobTable jt{};
+            jt.one = jobs[jx];
+            jt.njobs = 0;
+            if (launch_merge(jt, jobs[jx].out_words, stream)) return PA_EDEVICE;
+            stats->launches += 1;
+        }
+    if (hipStreamSynchronize(stream) != hipSuccess) return PA_EDEVICE;
+    return result;
+}
+
+int policy_of(uint32_t flags) {
+    switch (flags & PA_PREC_MASK) {
+        case PA_PREC_AUTO: return PREC_FP32;
+        case PA_PREC_FP32_SEG: return PREC_FP32;
+        case PA_PREC_FP64: return PREC_FP64;
+        case PA_PREC_NTT: return PREC_NTT;
+    }
+    return -1;
+}
+
+uint32_t prec_flag(int prec) {
+    return prec == PREC_FP32 ? PA_PREC_FP32_SEG : prec == PREC_FP64 ? PA_PREC_FP64 : PA_PREC_NTT;
+}
+
+void fill_plan_stats(pa_stats* s, const TilePlan& p) {
+    ClassGeom g;
+    class_geometry(p.prec, p.logL, &g);
+    s->prec = prec_flag(p.prec);
+    s->log2_len = (uint32_t)p.logL;
+    s->n1 = (uint32_t)g.n1;
+    s->n2 = (uint32_t)g.n2;
+    s->chunk_bits = p.Bi;
+    s->window_bits = p.Bo;
+    s->bound = std::max(s->bound, p.bound);
+    s->model_bytes += p.tiles() * ((p.prec == PREC_FP64 ? 48ull : 24ull) << p.logL);
+}
+
+}  // namespace pa
+
+// ================================================================ C ABI
+
+extern "C" {
+
+const char* pa_strerror(pa_status s) { return status_name(s); }
+
+pa_status pa_create(pa_ctx** out, int device, uint64_t budget, void* hip_stream) {
+    if (!out) return PA_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        return PA_EDEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) return PA_EDEVICE;
+    Ctx* c = new Ctx();
+    c->device = device;
+    c->budget = budget ? budget : (8ull << 30);
+    if (hip_stream) {
+        c->main.stream = (hipStream_t)hip_stream;
+        c->main.own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&c->main.stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return PA_EDEVICE;
+        }
+        c->main.own_stream = true;
+    }
+    c->serving_init();
+    *out = reinterpret_cast<pa_ctx*>(c);
+    return PA_OK;
+}
+
+void pa_destroy(pa_ctx* ctx) {
+    if (!ctx) return;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    (void)hipSetDevice(c->device);
+    c->serving_shutdown();
+    c->main.release(c);
+    c->serving_release();
+    for (auto& kv : c->tabs) kv.second.buf.release(c);
+    delete c;
+}
+
+static bool job_args_ok(const void* seed, const void* key, const void* out, uint64_t n, uint64_t m) {
+    return seed && key && out && n > 0 && m > 0 && n <= (1ull << 40) && m <= (1ull << 40);
+}
+
+pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, const uint64_t* key, uint64_t* out,
+                  uint32_t flags) {
+    if (!ctx || !job_args_ok(seed, key, out, n, m)) return PA_EINVAL;
+    const int policy = policy_of(flags);
+    if (policy < 0) return PA_EINVAL;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return PA_EDEVICE;
+    Lane& ln = c->main;
+    pa_stats st{};
+    TilePlan plan;
+    if (!plan_job(n, m, policy, c->cost, &plan)) return PA_EINVAL;
+    fill_plan_stats(&st, plan);
+
+    const uint64_t sw = words_of(n + m - 1), kw = words_of(n), ow = words_of(m);
+    const uint64_t *dseed = seed, *dkey = key;
+    uint64_t* dout = out;
+    const bool dev = flags & PA_DEVICE_PTRS;
+    if (!dev) {  // stage host buffers through library memory
+        pa_status s = ln.io.ensure(c, (sw + kw + ow) * 8);
+        if (s != PA_OK) return s;
+        uint64_t* base = (uint64_t*)ln.io.ptr;
+        if (hipMemcpyAsync(base, seed, sw * 8, hipMemcpyHostToDevice, ln.stream) != hipSuccess ||
+            hipMemcpyAsync(base + sw, key, kw * 8, hipMemcpyHostToDevice, ln.stream) != hipSuccess)
+            return PA_EDEVICE;
+        dseed = base;
+        dkey = base + sw;
+        dout = base + sw + kw;
+    }
+    std::vector<JobDesc> jobs(1);
+    fill_job(&jobs[0], dseed, dkey, dout, n, m, plan);
+    // Only an a-priori certified plan may skip the certificate read-back.
+    const bool async = dev && (flags & PA_ASYNC) && plan.prec == PREC_FP64;
+    const bool timing = flags & PA_TIMING;
+    pa_status s = ln.launch(c, plan.prec, plan.logL, jobs, timing, !async, &st);
+    if (s == PA_OK && !async) s = ln.finish(c, flags, &st, nullptr);
+    if (s == PA_OK && !dev) {
+        if (hipMemcpyAsync(out, dout, ow * 8, hipMemcpyDeviceToHost, ln.stream) != hipSuccess ||
+            hipStreamSynchronize(ln.stream) != hipSuccess)
+            s = PA_EDEVICE;
+    }
+    c->last = st;
+    return s;
+}
+
+pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint32_t flags, pa_status* per_job) {
+    if (!ctx || (!jobs_in && count)) return PA_EINVAL;
+    if (count == 0) return PA_OK;
+    if (count > 65535) return PA_EINVAL;
+    const int policy = policy_of(flags);
+    if (policy < 0) return PA_EINVAL;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    std::vector<uint64_t> ns, ms;
+    for (uint64_t i = 0; i < count; ++i) {
+        const pa_job& j = jobs_in[i];
+        if (!job_args_ok(j.seed, j.key, j.out, j.n, j.m)) {
+            if (per_job)
+                for (uint64_t k = 0; k < count; ++k) per_job[k] = k == i ? PA_EINVAL : PA_OK;
+            return PA_EINVAL;
+        }
+        ns.push_back(j.n);
+        ms.push_back(j.m);
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return PA_EDEVICE;
+    Lane& ln = c->main;
+    int logL = 0;
+    std::vector<TilePlan> plans;
+    if (!plan_batch(ns, ms, policy, c->cost, &logL, &plans)) return PA_EINVAL;
+    pa_stats st{};
+    for (const TilePlan& p : plans) fill_plan_stats(&st, p);
+    st.chunk_bits = 0;   // differ per job
+    st.window_bits = 0;
+
+    const bool dev = flags & PA_DEVICE_PTRS;
+    std::vector<JobDesc> jobs(count);
+    std::vector<uint64_t> out_off(count, 0);
+    if (!dev) {
+        uint64_t total_words = 0;
+        for (uint64_t i = 0; i < count; ++i)
+            total_words += words_of(ns[i] + ms[i] - 1) + words_of(ns[i]) + words_of(ms[i]);
+        pa_status s = ln.io.ensure(c, total_words * 8);
+        if (s != PA_OK) return s;
+    }
+    uint64_t off = 0;
+    for (uint64_t i = 0; i < count; ++i) {
+        const pa_job& j = jobs_in[i];
+        const uint64_t *dseed = j.seed, *dkey = j.key;
+        uint64_t* dout = j.out;
+        if (!dev) {
+            uint64_t* base = (uint64_t*)ln.io.ptr + off;
+            const uint64_t sw = words_of(j.n + j.m - 1), kw = words_of(j.n), ow = words_of(j.m);
+            if (hipMemcpyAsync(base, j.seed, sw * 8, hipMemcpyHostToDevice, ln.stream) != hipSuccess ||
+                hipMemcpyAsync(base + sw, j.key, kw * 8, hipMemcpyHostToDevice, ln.stream) != hipSuccess)
+                return PA_EDEVICE;
+            dseed = base;
+            dkey = base + sw;
+            dout = base + sw + kw;
+            out_off[i] = off + sw + kw;
+            off += sw + kw + ow;
+        }
+        fill_job(&jobs[i], dseed, dkey, dout, j.n, j.m, plans[i]);
+    }
+    std::vector<pa_status> status(count, PA_OK);
+    pa_status s = ln.launch(c, plans[0].prec, logL, jobs, flags & PA_TIMING, true, &st);
+    if (s == PA_OK) s = ln.finish(c, flags, &st, &status);
+    if (!dev && (s == PA_OK || s == PA_EPRECISION)) {
+        for (uint64_t i = 0; i < count; ++i)
+            if (hipMemcpyAsync(jobs_in[i].out, (uint64_t*)ln.io.ptr + out_off[i], words_of(ms[i]) * 8,
+                               hipMemcpyDeviceToHost, ln.stream) != hipSuccess)
+                s = PA_EDEVICE;
+        if (hipStreamSynchronize(ln.stream) != hipSuccess) s = PA_EDEVICE;
+    }
+    if (per_job)
+        for (uint64_t i = 0; i < count; ++i) per_job[i] = (s == PA_OK || s == PA_EPRECISION) ? status[i] : s;
+    c->last = st;
+    return s;
+}
+
+pa_status pa_last_stats(pa_ctx* ctx, pa_stats* out) {
+    if (!ctx || !out) return PA_EINVAL;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    std::lock_guard<std::mutex> lk(c->mu);
+    *out = c->last;
+    return PA_OK;
+}
+
+pa_status pa_plan_query(uint64_t n, uint64_t m, uint32_t flags, pa_plan* out) {
+    if (!out || n == 0 || m == 0) return PA_EINVAL;
+    const int policy = policy_of(flags);
+    if (policy < 0) return PA_EINVAL;
+    CostModel cm;
+    TilePlan p;
+    if (!plan_job(n, m, policy, cm, &p)) return PA_EINVAL;
+    ClassGeom g;
+    class_geometry(p.prec, p.logL, &g);
+    out->prec = prec_flag(p.prec);
+    out->log2_len = (uint32_t)p.logL;
+    out->n1 = (uint32_t)g.n1;
+    out->n2 = (uint32_t)g.n2;
+    out->chunk_bits = p.Bi;
+    out->window_bits = p.Bo;
+    out->chunks = p.nchunks;
+    out->windows = p.nouts;
+    out->bound = p.bound;
+    out->cost = p.cost;
+    return PA_OK;
+}
+
+double pa_error_model(uint32_t prec, uint32_t log2_len, uint64_t chunk_bits) {
+    const int p = policy_of(prec);
+    if (p < 0) return -1.0;
+    return error_bound(p, (int)log2_len, chunk_bits);
+}
+
+}  // extern "C"

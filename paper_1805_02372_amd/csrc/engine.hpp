@@ -1,0 +1,132 @@
+// Host engine internals of libpa (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "pa.h"
+#include "pa_internal.hpp"
+#include "planner.hpp"
+
+namespace pa {
+
+struct Ctx;
+
+// Device allocation charged to the context's HBM budget.
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    pa_status ensure(Ctx* c, size_t need);
+    void release(Ctx* c);
+};
+
+// Pinned host allocation (staging of descriptors and certificates).
+struct HostBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    pa_status ensure(size_t need);
+    void release();
+};
+
+struct DevTables {
+    DevBuf buf;
+    Tables t;
+};
+
+// Events bracketing the passes of one launch (PA_TIMING).
+struct PassTimer {
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> spans;  // pass index, (start, stop)
+    size_t used = 0;
+    hipEvent_t mark(hipStream_t s);
+    void reset() { used = 0; spans.clear(); }
+    void collect(double ms[4]);
+    void destroy();
+};
+
+// A stream with its own workspace: runs one plan at a time.
+struct Lane {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    DevBuf ws, part, meta, jobs_dev, stage, io;
+    HostBuf meta_host, jobs_host;
+    PassTimer timer;
+
+    // In-flight state of an asynchronous launch (serving).
+    int prec = 0, logL = 0;
+    uint32_t total_tiles = 0;
+    std::vector<JobDesc> jobs;
+    hipEvent_t done = nullptr;
+
+    void release(Ctx* c);
+
+    // Enqueue every tile of `jobs` (planned at class prec/logL) and the merge;
+    // sets tile_begin and stage pointers.  With `fetch_meta` the tile
+    // certificates are copied to meta_host behind the kernels.
+    pa_status launch(Ctx* c, int prec, int logL, std::vector<JobDesc>& jobs, bool timing, bool fetch_meta,
+                     pa_stats* stats);
+    // After the launch completed: check certificates, re-run failed FP32
+    // tiles in FP64, re-merge.  Synchronous on this lane's stream.
+    pa_status finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_status>* per_job);
+};
+
+// One serving request.
+struct Request {
+    uint64_t ticket = 0;
+    uint32_t seed_id = 0;
+    uint64_t n = 0, m = 0;
+    const uint64_t* key = nullptr;
+    uint64_t* out = nullptr;
+    double t_submit = 0, t_done = 0;
+    pa_status status = PA_OK;
+    int state = 0;  // 0 queued, 1 running, 2 done
+};
+
+struct Ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    std::atomic<uint64_t> used{0};
+    std::mutex mu;        // serialises the public calls that use `main`
+    std::mutex tab_mu;    // twiddle table cache
+    Lane main;
+    std::map<int, DevTables> tabs;
+    CostModel cost;
+    pa_stats last{};
+
+    pa_status tables(int prec, int logL, Tables* out);
+
+    // ---- serving
+    std::mutex smu;
+    std::condition_variable scv, done_cv;
+    std::deque<Request*> pending;
+    std::map<uint64_t, Request*> requests;
+    std::vector<DevBuf> seeds;
+    std::vector<uint64_t> seed_bits;
+    std::vector<Lane> lanes;
+    std::vector<std::vector<Request*>> lane_reqs;
+    std::thread worker;
+    bool stop = false, worker_started = false;
+    uint64_t next_ticket = 1;
+    size_t queue_cap = 1 << 16;
+    void serving_init();
+    void serving_shutdown();
+    void serving_release();
+    void serve_loop();
+};
+
+const char* status_name(pa_status s);
+int policy_of(uint32_t flags);
+uint32_t prec_flag(int prec);
+void fill_plan_stats(pa_stats* s, const TilePlan& p);
+void fill_job(JobDesc* jd, const uint64_t* seed, const uint64_t* key, uint64_t* out, uint64_t n, uint64_t m,
+              const TilePlan& p);
+double now_seconds();
+
+}  // namespace pa

@@ -1,0 +1,79 @@
+// Shared host/device declarations of libpa (not part of the public ABI).
+#pragma once
+#include <stdint.h>
+#include <stddef.h>
+
+namespace pa {
+
+// One hash job as the kernels see it.  A job is cut into `nchunks` key chunks
+// (taken from the top of the key: chunk b covers key bits
+// [max(0, n-(b+1)Bi), n-b*Bi)) and `nouts` output windows (window o covers
+// outputs [o*Bo, min(m, (o+1)*Bo))); tile (b, o) is local tile b*nouts + o.
+// Tile (b, o) with chunk start j0, length bi, window start i0, length bo uses
+// seed bits [sigma, sigma+bi+bo-1) with sigma = i0 - j0 + n - bi: by the
+// constant diagonals of T its outputs are the window [bi-1, bi-1+bo) of the
+// convolution of that seed slice with the key chunk (Eq. 4-6, Fig. 1-2).
+struct JobDesc {
+    const uint64_t* key;
+    const uint64_t* seed;
+    uint64_t* out;        // m bits
+    uint64_t* stage;      // nchunks rows of out_words words (nchunks > 1), else null
+    uint64_t n, m;
+    uint64_t Bi, Bo;      // nominal chunk and window lengths (Bo % 64 == 0 if nouts > 1)
+    uint32_t nchunks, nouts;
+    uint32_t tile_begin;  // first tile of this job in the launch's tile numbering
+    uint32_t out_words;   // ceil(m / 64)
+};
+
+// Where the tiles of one launch come from: either one job passed by value or
+// an array of jobs (sorted by tile_begin) in device memory.
+struct JobTable {
+    JobDesc one;
+    const JobDesc* many;
+    uint32_t njobs;       // 0: use `one`
+    uint32_t tile0;       // first tile of this launch (groups of tiles)
+    uint32_t ntiles;      // tiles in this launch
+};
+
+// Per-tile results of pass 2/3.
+struct TileMeta {
+    uint32_t popcnt;      // weight of the key chunk
+    uint32_t maxres;      // float bits of max |z - rint z|
+    uint32_t maxabs;      // float bits of max |z|
+    uint32_t badpar;      // outputs whose rounded value had the wrong parity
+};
+
+// One FFT length class: L = n1 * n2 = 2^logL.
+struct ClassCfg {
+    int prec;             // 32 or 64
+    int logL;
+    int n1, n2;           // row length (pass 2), column length (pass 1/3)
+    int b1, b3;           // columns per workgroup in pass 1 / pass 3
+    int r;                // points per thread
+};
+
+// Device pointers of a class's twiddle tables (element type matches prec).
+struct Tables {
+    const void* tw;       // w_NT^e, e < NT = max(n1, n2)
+    const void* fa;       // w_L^{h << fshift}, h < L >> fshift
+    const void* fb;       // w_L^l, l < 1 << fshift
+    int fshift;
+};
+
+typedef int (*launch_fn)(const JobTable& jt, void* ws, uint32_t* part, TileMeta* meta,
+                         const Tables& tb, void* stream);
+
+struct ClassKernels {
+    ClassCfg cfg;
+    launch_fn pass1, pass2, pass3;
+};
+
+// Registered by the per-precision kernel objects.
+const ClassKernels* class_kernels(int prec, int logL);
+int launch_merge(const JobTable& jt, uint64_t max_words, void* stream);
+
+constexpr int kMinLogL = 12;
+constexpr int kMaxLogL32 = 24;
+constexpr int kMaxLogL64 = 24;
+
+}  // namespace pa

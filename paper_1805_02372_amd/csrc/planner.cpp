@@ -1,0 +1,177 @@
+// Tile planning (paper section 3, step 2: choose the number of blocks and
+// batches from the input length, the device memory and the precision the FFT
+// needs).  Here a job is cut into key chunks (the paper's blocks/batches, Eq.
+// 4-5) and, when the output is long, output windows; every tile of a plan uses
+// one FFT length class.
+#include "planner.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+
+namespace pa {
+
+namespace {
+double g_kappa = 1.0;
+
+int prec_index(int prec) { return prec == PREC_FP32 ? 0 : prec == PREC_FP64 ? 1 : 2; }
+
+uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+uint64_t round_up64(uint64_t a) { return (a + 63) & ~uint64_t(63); }
+}  // namespace
+
+int min_logL(int) { return 12; }
+
+// Largest class; PA_MAX_LOG2_LEN (12..24) lowers it, e.g. to force key
+// chunking and output windows on small inputs.
+int max_logL(int prec) {
+    (void)prec;
+    int cap = 24;
+    if (const char* e = getenv("PA_MAX_LOG2_LEN")) {
+        int v = atoi(e);
+        if (v >= 12 && v < cap) cap = v;
+    }
+    return cap;
+}
+
+bool class_geometry(int prec, int logL, ClassGeom* g) {
+    if (logL < 12 || logL > 24) return false;
+    int n2cap = prec == PREC_FP64 ? 11 : 10;
+    int n2log = std::max(logL - 13, std::min(n2cap, logL / 2));
+    g->prec = prec;
+    g->logL = logL;
+    g->n2 = 1 << n2log;
+    g->n1 = 1 << (logL - n2log);
+    g->b1 = prec == PREC_FP64 ? 4 : 8;
+    g->b3 = prec == PREC_FP64 ? 8 : 16;
+    g->r = 16;
+    return true;
+}
+
+void set_error_kappa(double kappa) { g_kappa = kappa; }
+double error_kappa() { return g_kappa; }
+
+static double unit_roundoff(int prec) {
+    return prec == PREC_FP32 ? std::ldexp(1.0, -24) : prec == PREC_FP64 ? std::ldexp(1.0, -53) : 0.0;
+}
+
+double error_bound(int prec, int logL, uint64_t Bi) {
+    if (prec == PREC_NTT) return 0.0;
+    return 6.0 * g_kappa * unit_roundoff(prec) * std::sqrt((double)logL * (double)Bi);
+}
+
+double rigorous_bound(int prec, int logL, uint64_t Bi, uint64_t Bo) {
+    if (prec == PREC_NTT) return 0.0;
+    const double u = unit_roundoff(prec), k = (double)logL, beta = 2.0 * u;
+    const double g = 3 * k * std::log1p(u) + (3 * k + 1) * std::log1p(u * std::sqrt(5.0)) +
+                     3 * k * std::log1p(beta);
+    return std::sqrt((double)Bi) * std::sqrt((double)(Bi + Bo - 1)) * std::expm1(g);
+}
+
+CostModel::CostModel() {
+    launch_s = 12e-6;
+    for (int p = 0; p < 3; ++p)
+        for (int k = 0; k < 32; ++k) {
+            const double L = std::ldexp(1.0, k);
+            // bytes moved by the three passes and a VALU estimate
+            const double bytes = (p == 1 ? 48.0 : 24.0) * L;
+            const double instr = L * (5.0 * k + 40.0) * (p == 2 ? 3.0 : 1.0);
+            const double t_mem = bytes / 5.0e12, t_alu = instr / 20.0e12;
+            tile_s[p][k] = std::max(t_mem, t_alu) + 1e-6;
+        }
+}
+
+double CostModel::tile(int prec, int logL) const { return tile_s[prec_index(prec)][logL]; }
+void CostModel::set(int prec, int logL, double s) { tile_s[prec_index(prec)][logL] = s; }
+
+bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& cm, TilePlan* out) {
+    ClassGeom g;
+    if (n == 0 || m == 0 || !class_geometry(prec, logL, &g)) return false;
+    const uint64_t L = 1ull << logL;
+    // largest chunk the error model admits at this length
+    uint64_t bi_cap = n;
+    if (prec != PREC_NTT) {
+        const double per = 6.0 * g_kappa * unit_roundoff(prec) * std::sqrt((double)logL);
+        const double cap = std::floor((kPlanErrorLimit / per) * (kPlanErrorLimit / per));
+        if (cap < (double)bi_cap) bi_cap = (uint64_t)std::max(0.0, cap);
+    }
+    TilePlan best;
+    bool found = false;
+    const uint64_t max_outs = std::min<uint64_t>(ceil_div(m, 64), 1u << 14);
+    uint64_t last_bo = 0;
+    for (uint64_t w = 1; w <= std::max<uint64_t>(1, max_outs); ++w) {
+        uint64_t Bo = (w == 1) ? m : round_up64(ceil_div(m, w));
+        if (Bo == last_bo) continue;
+        last_bo = Bo;
+        if (Bo > L) continue;
+        const uint64_t nouts = ceil_div(m, Bo);
+        uint64_t bi_max = std::min<uint64_t>(L - Bo + 1, bi_cap);
+        if (bi_max == 0) continue;
+        const uint64_t nchunks = ceil_div(n, bi_max);
+        const uint64_t Bi = ceil_div(n, nchunks);
+        const uint64_t tiles = nchunks * nouts;
+        if (!found || tiles < best.tiles()) {
+            found = true;
+            best.prec = prec;
+            best.logL = logL;
+            best.Bi = Bi;
+            best.Bo = Bo;
+            best.nchunks = nchunks;
+            best.nouts = nouts;
+        }
+        if (nouts == 1 && nchunks == 1) break;
+    }
+    if (!found) return false;
+    best.bound = error_bound(prec, logL, best.Bi);
+    best.cost = (double)best.tiles() * cm.tile(prec, logL) + cm.launch_s;
+    *out = best;
+    return true;
+}
+
+bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan* out) {
+    if (n == 0 || m == 0) return false;
+    const int prec = policy;
+    if (prec == PREC_FP64 || prec == PREC_NTT) {
+        // one tile at the smallest class that holds the whole product
+        for (int k = min_logL(prec); k <= max_logL(prec); ++k)
+            if (n + m - 1 <= (1ull << k)) return plan_at_class(n, m, prec, k, cm, out);
+    }
+    bool found = false;
+    TilePlan best;
+    for (int k = min_logL(prec); k <= max_logL(prec); ++k) {
+        TilePlan p;
+        if (!plan_at_class(n, m, prec, k, cm, &p)) continue;
+        if (!found || p.cost < best.cost) {
+            best = p;
+            found = true;
+        }
+    }
+    if (found) *out = best;
+    return found;
+}
+
+bool plan_batch(const std::vector<uint64_t>& ns, const std::vector<uint64_t>& ms, int policy,
+                const CostModel& cm, int* logL_out, std::vector<TilePlan>* plans) {
+    if (ns.empty() || ns.size() != ms.size()) return false;
+    bool found = false;
+    double best_cost = 0;
+    std::vector<TilePlan> tmp(ns.size());
+    for (int k = min_logL(policy); k <= max_logL(policy); ++k) {
+        double cost = cm.launch_s;
+        bool ok = true;
+        for (size_t i = 0; i < ns.size() && ok; ++i) {
+            ok = plan_at_class(ns[i], ms[i], policy, k, cm, &tmp[i]);
+            if (ok) cost += tmp[i].cost - cm.launch_s;
+        }
+        if (!ok) continue;
+        if (!found || cost < best_cost) {
+            found = true;
+            best_cost = cost;
+            *logL_out = k;
+            *plans = tmp;
+        }
+    }
+    return found;
+}
+
+}  // namespace pa

@@ -1,0 +1,63 @@
+// Tile planning: FFT length class, key-chunk and output-window sizes, and the
+// rounding-error model that bounds them.  Pure host code.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace pa {
+
+enum Prec { PREC_FP32 = 32, PREC_FP64 = 64, PREC_NTT = 1 };
+
+struct ClassGeom {
+    int prec, logL, n1, n2, b1, b3, r;
+};
+
+// Geometry of the length class 2^logL in the given precision; false if none.
+bool class_geometry(int prec, int logL, ClassGeom* g);
+int min_logL(int prec);
+int max_logL(int prec);
+
+// Cost per tile (seconds) of a class, by prec and logL.  Filled from tuning
+// data when present, else from the built-in model.
+struct CostModel {
+    double tile_s[3][32];   // [0] FP32, [1] FP64, [2] NTT; index logL
+    double launch_s;        // fixed cost of one pipeline launch
+    CostModel();
+    double tile(int prec, int logL) const;
+    void set(int prec, int logL, double s);
+};
+
+struct TilePlan {
+    int prec = 0, logL = 0;
+    uint64_t Bi = 0, Bo = 0, nchunks = 0, nouts = 0;
+    double bound = 0, cost = 0;
+    uint64_t tiles() const { return nchunks * nouts; }
+};
+
+// Probabilistic error model of one floating-point tile: about 6 standard
+// deviations of the output error for an FFT convolution of a +-1 sequence
+// with a 0/1 chunk of Bi bits at length 2^logL, sigma = kappa u sqrt(logL Bi).
+double error_bound(int prec, int logL, uint64_t Bi);
+// Worst-case (a-priori) bound: ||x|| ||w|| times the relative error growth of
+// the FFT, product and inverse FFT, with ||x|| <= sqrt(Bi), ||w|| = sqrt(Bi+Bo-1).
+double rigorous_bound(int prec, int logL, uint64_t Bi, uint64_t Bo);
+void set_error_kappa(double kappa);
+double error_kappa();
+
+// The admissible error for a floating-point plan before the a-posteriori
+// certificate (half the rounding margin of 0.5).
+constexpr double kPlanErrorLimit = 0.25;
+
+// Best (Bi, Bo) for job (n, m) at a fixed class; false if impossible.
+bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& cm, TilePlan* out);
+
+// Best plan over classes for one job.  policy: PREC_FP32 (segmented, bound
+// limited), PREC_FP64 (smallest single tile if one fits, else the largest
+// class), PREC_NTT.
+bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan* out);
+
+// One class for a whole batch: minimises the summed cost of every job's tiles.
+bool plan_batch(const std::vector<uint64_t>& ns, const std::vector<uint64_t>& ms, int policy,
+                const CostModel& cm, int* logL, std::vector<TilePlan>* plans);
+
+}  // namespace pa

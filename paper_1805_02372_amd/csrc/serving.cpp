@@ -1,0 +1,261 @@
+// Serving: resident seeds, a request queue, and a worker that keeps several
+// lanes (streams with their own workspace) busy.  Whenever a lane is free and
+// requests are waiting, the worker admits the oldest requests that fit the
+// lane's share of the HBM budget into one batched launch (one pipeline launch
+// for all their tiles); requests that arrive while batches run join the next
+// launch on whichever lane frees first, so their work overlaps on the device
+// with the batches already running.  The paper motivates this by real-time
+// CV-QKD with keys already resident on the GPU (section 3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+
+#include "engine.hpp"
+
+namespace pa {
+
+double now_seconds() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+static uint64_t words_of(uint64_t bits) { return (bits + 63) >> 6; }
+
+void Ctx::serving_init() {}
+
+static int serve_lanes() {
+    const char* e = getenv("PA_SERVE_LANES");
+    int v = e ? atoi(e) : 2;
+    return std::max(1, std::min(v, 8));
+}
+
+void Ctx::serving_shutdown() {
+    {
+        std::lock_guard<std::mutex> lk(smu);
+        stop = true;
+    }
+    scv.notify_all();
+    if (worker_started && worker.joinable()) worker.join();
+    worker_started = false;
+}
+
+void Ctx::serving_release() {
+    for (Lane& ln : lanes) ln.release(this);
+    lanes.clear();
+    for (DevBuf& b : seeds) b.release(this);
+    seeds.clear();
+    for (auto& kv : requests) delete kv.second;
+    requests.clear();
+    pending.clear();
+}
+
+// Tile-workspace bytes of a request at its own best FP32 plan (all tiles
+// resident at once; a launch runs fewer at a time if the budget is short).
+static uint64_t request_bytes(const CostModel& cm, uint64_t n, uint64_t m, uint64_t* min_bytes) {
+    TilePlan p;
+    if (!plan_job(n, m, PREC_FP32, cm, &p)) {
+        *min_bytes = ~0ull;
+        return ~0ull;
+    }
+    *min_bytes = (uint64_t)8 << p.logL;
+    return p.tiles() * *min_bytes;
+}
+
+void Ctx::serve_loop() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(smu);
+    std::vector<pa_stats> lane_stats(lanes.size());
+    std::vector<uint8_t> busy(lanes.size(), 0);
+    const uint64_t lane_budget = budget / (lanes.size() + 1);
+    while (true) {
+        bool any_busy = false;
+        // completions
+        for (size_t i = 0; i < lanes.size(); ++i) {
+            if (!busy[i]) continue;
+            if (hipEventQuery(lanes[i].done) == hipErrorNotReady) {
+                any_busy = true;
+                continue;
+            }
+            (void)hipGetLastError();
+            std::vector<Request*> reqs = lane_reqs[i];
+            std::vector<pa_status> per(reqs.size(), PA_OK);
+            lk.unlock();
+            pa_status s = lanes[i].finish(this, 0, &lane_stats[i], &per);
+            const double t = now_seconds();
+            lk.lock();
+            for (size_t k = 0; k < reqs.size(); ++k) {
+                reqs[k]->status = (s == PA_OK || s == PA_EPRECISION) ? per[k] : s;
+                reqs[k]->t_done = t;
+                reqs[k]->state = 2;
+            }
+            lane_reqs[i].clear();
+            busy[i] = 0;
+            done_cv.notify_all();
+        }
+        // admissions
+        for (size_t i = 0; i < lanes.size() && !pending.empty() && !stop; ++i) {
+            if (busy[i]) continue;
+            std::vector<Request*> batch;
+            uint64_t bytes = 0;
+            while (!pending.empty() && batch.size() < 4096) {
+                Request* r = pending.front();
+                uint64_t bmin = 0;
+                const uint64_t b = request_bytes(cost, r->n, r->m, &bmin);
+                if (!batch.empty() && bytes + b > lane_budget) break;
+                pending.pop_front();
+                if (bmin > budget) {
+                    r->status = PA_ENOMEM;
+                    r->t_done = now_seconds();
+                    r->state = 2;
+                    done_cv.notify_all();
+                    continue;
+                }
+                r->state = 1;
+                bytes += b;
+                batch.push_back(r);
+            }
+            if (batch.empty()) continue;
+            std::vector<uint64_t> ns, ms;
+            for (Request* r : batch) {
+                ns.push_back(r->n);
+                ms.push_back(r->m);
+            }
+            lk.unlock();
+            int logL = 0;
+            std::vector<TilePlan> plans;
+            pa_status s = plan_batch(ns, ms, PREC_FP32, cost, &logL, &plans) ? PA_OK : PA_EINVAL;
+            std::vector<JobDesc> jobs(batch.size());
+            if (s == PA_OK) {
+                for (size_t k = 0; k < batch.size(); ++k)
+                    fill_job(&jobs[k], (const uint64_t*)seeds[batch[k]->seed_id].ptr, batch[k]->key, batch[k]->out,
+                             batch[k]->n, batch[k]->m, plans[k]);
+                lane_stats[i] = pa_stats{};
+                s = lanes[i].launch(this, PREC_FP32, logL, jobs, false, true, &lane_stats[i]);
+            }
+            lk.lock();
+            if (s != PA_OK) {
+                const double t = now_seconds();
+                for (Request* r : batch) {
+                    r->status = s;
+                    r->t_done = t;
+                    r->state = 2;
+                }
+                done_cv.notify_all();
+            } else {
+                lane_reqs[i] = batch;
+                busy[i] = 1;
+                any_busy = true;
+            }
+        }
+        if (stop && !any_busy) break;
+        if (any_busy)
+            scv.wait_for(lk, std::chrono::microseconds(20));
+        else if (pending.empty())
+            scv.wait(lk, [&] { return stop || !pending.empty(); });
+    }
+}
+
+}  // namespace pa
+
+using namespace pa;
+
+extern "C" {
+
+pa_status pa_seed_register(pa_ctx* ctx, const uint64_t* seed, uint64_t nbits, uint32_t flags, uint32_t* seed_id) {
+    if (!ctx || !seed || !seed_id || nbits == 0) return PA_EINVAL;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (hipSetDevice(c->device) != hipSuccess) return PA_EDEVICE;
+    DevBuf b;
+    const size_t bytes = words_of(nbits) * 8;
+    pa_status st = b.ensure(c, bytes);
+    if (st != PA_OK) return st;
+    const hipMemcpyKind kind = (flags & PA_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (hipMemcpy(b.ptr, seed, bytes, kind) != hipSuccess) {
+        b.release(c);
+        return PA_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(c->smu);
+    c->seeds.push_back(b);
+    c->seed_bits.push_back(nbits);
+    *seed_id = (uint32_t)(c->seeds.size() - 1);
+    return PA_OK;
+}
+
+pa_status pa_submit(pa_ctx* ctx, uint32_t seed_id, uint64_t n, uint64_t m, const uint64_t* key, uint64_t* out,
+                    uint64_t* ticket) {
+    if (!ctx || !key || !out || !ticket || n == 0 || m == 0) return PA_EINVAL;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    std::unique_lock<std::mutex> lk(c->smu);
+    if (seed_id >= c->seeds.size() || n + m - 1 > c->seed_bits[seed_id]) return PA_EINVAL;
+    if (c->pending.size() >= c->queue_cap) return PA_EBUSY;
+    if (!c->worker_started) {
+        lk.unlock();
+        if (hipSetDevice(c->device) != hipSuccess) return PA_EDEVICE;
+        std::vector<Lane> lanes(serve_lanes());
+        for (Lane& ln : lanes) {
+            if (hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) != hipSuccess) return PA_EDEVICE;
+            ln.own_stream = true;
+        }
+        lk.lock();
+        if (!c->worker_started) {
+            c->lanes = std::move(lanes);
+            c->lane_reqs.assign(c->lanes.size(), {});
+            c->stop = false;
+            c->worker = std::thread([c] { c->serve_loop(); });
+            c->worker_started = true;
+        } else {
+            for (Lane& ln : lanes) ln.release(c);
+        }
+    }
+    Request* r = new Request();
+    r->ticket = c->next_ticket++;
+    r->seed_id = seed_id;
+    r->n = n;
+    r->m = m;
+    r->key = key;
+    r->out = out;
+    r->t_submit = now_seconds();
+    c->requests[r->ticket] = r;
+    c->pending.push_back(r);
+    *ticket = r->ticket;
+    lk.unlock();
+    c->scv.notify_all();
+    return PA_OK;
+}
+
+pa_status pa_poll(pa_ctx* ctx, uint64_t ticket, int* done) {
+    if (!ctx || !done) return PA_EINVAL;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    std::lock_guard<std::mutex> lk(c->smu);
+    auto it = c->requests.find(ticket);
+    if (it == c->requests.end()) return PA_EINVAL;
+    *done = it->second->state == 2;
+    return PA_OK;
+}
+
+pa_status pa_wait(pa_ctx* ctx, uint64_t ticket) {
+    if (!ctx) return PA_EINVAL;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    std::unique_lock<std::mutex> lk(c->smu);
+    auto it = c->requests.find(ticket);
+    if (it == c->requests.end()) return PA_EINVAL;
+    Request* r = it->second;
+    c->done_cv.wait(lk, [&] { return r->state == 2; });
+    return r->status;
+}
+
+pa_status pa_ticket_latency(pa_ctx* ctx, uint64_t ticket, double* seconds) {
+    if (!ctx || !seconds) return PA_EINVAL;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    std::lock_guard<std::mutex> lk(c->smu);
+    auto it = c->requests.find(ticket);
+    if (it == c->requests.end()) return PA_EINVAL;
+    if (it->second->state != 2) return PA_ENOTREADY;
+    *seconds = it->second->t_done - it->second->t_submit;
+    return PA_OK;
+}
+
+}  // extern "C"

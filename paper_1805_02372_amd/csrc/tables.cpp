@@ -1,0 +1,55 @@
+// Twiddle tables, computed on the host in extended precision and rounded once
+// to the working precision.
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "tables.hpp"
+
+namespace pa {
+
+// exp(-2 pi i e / N) = c + i s.  The angle is reduced to the nearest quarter
+// turn first, so multiples of pi/2 come out exact and the table is symmetric.
+void unit_root(uint64_t e, uint64_t N, long double* c, long double* s) {
+    e %= N;
+    // e/N = q/4 + d/N with |d/N| <= 1/8
+    const uint64_t q = (4 * e + N / 2) / N;        // nearest quarter turn
+    const long double d = (long double)e - (long double)q * (long double)N / 4.0L;
+    const long double th = 2.0L * 3.14159265358979323846264338327950288L * d / (long double)N;
+    const long double cd = cosl(th), sd = sinl(th);
+    long double cc, ss;  // cos and sin of the full angle
+    switch (q & 3) {
+        case 0: cc = cd; ss = sd; break;
+        case 1: cc = -sd; ss = cd; break;
+        case 2: cc = -cd; ss = -sd; break;
+        default: cc = sd; ss = -cd; break;
+    }
+    *c = cc;
+    *s = -ss;
+}
+
+template <typename T>
+static void roots(std::vector<T>& out, uint64_t count, uint64_t N, uint64_t mult) {
+    out.resize(2 * count);
+    for (uint64_t e = 0; e < count; ++e) {
+        long double c, s;
+        unit_root(e * mult, N, &c, &s);
+        out[2 * e] = (T)c;
+        out[2 * e + 1] = (T)s;
+    }
+}
+
+template <typename T>
+void build_tables(int logL, int n1, int n2, TableHost<T>* th) {
+    const uint64_t L = 1ull << logL;
+    const uint64_t NT = (uint64_t)(n1 > n2 ? n1 : n2);
+    th->fshift = (logL + 1) / 2;
+    roots(th->tw, NT, NT, 1);
+    roots(th->fa, L >> th->fshift, L, 1ull << th->fshift);
+    roots(th->fb, 1ull << th->fshift, L, 1);
+}
+
+template void build_tables<float>(int, int, int, TableHost<float>*);
+template void build_tables<double>(int, int, int, TableHost<double>*);
+
+}  // namespace pa

@@ -1,0 +1,21 @@
+// Host-side twiddle tables (see tables.cpp).
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace pa {
+
+// exp(-2 pi i e / N) in long double.
+void unit_root(uint64_t e, uint64_t N, long double* c, long double* s);
+
+// Interleaved (re, im) tables of one FFT length class:
+//   tw[e] = w_NT^e, e < NT = max(n1, n2);
+//   fa[h] = w_L^{h << fshift}, fb[l] = w_L^l, so w_L^e = fa[e >> fshift] fb[e & mask].
+template <typename T> struct TableHost {
+    std::vector<T> tw, fa, fb;
+    int fshift = 0;
+};
+
+template <typename T> void build_tables(int logL, int n1, int n2, TableHost<T>* th);
+
+}  // namespace pa

@@ -1,0 +1,122 @@
+"""GPU path vs the CPU oracle, bit-exact, through the C ABI (MI355X)."""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "digests.json")))
+
+
+@pytest.fixture(scope="module")
+def pa():
+    from paper_1805_02372_amd import pa as _pa
+    return _pa
+
+
+@pytest.fixture(scope="module")
+def ctx(pa):
+    import torch
+    assert torch.cuda.is_available()
+    c = pa.pa_create(0, 0, None)
+    yield c
+    pa.pa_destroy(c)
+
+
+def _run(pa, ctx, p, flags):
+    from gpu_util import gpu_hash
+    print(f"case n={p.n} m={p.m} flags={flags:#x}", flush=True)
+    return gpu_hash(pa, ctx, p.seed, p.n, p.m, p.key, flags)
+
+
+SMALL = [(1, 1), (1, 100), (100, 1), (2, 3), (63, 65), (64, 64), (65, 63), (1000, 333), (333, 1000),
+         (4097, 511), (5000, 5000), (100_000, 3000), (70_000, 70_001), (131_071, 1), (1, 131_071)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "auto"])
+@pytest.mark.parametrize("n,m", SMALL)
+def test_small_shapes(pa, ctx, prec, n, m):
+    from gpu_util import describe
+    flags = {"fp64": pa.PA_PREC_FP64, "fp32": pa.PA_PREC_FP32_SEG, "auto": pa.PA_PREC_AUTO}[prec]
+    rng = np.random.default_rng(n * 1000003 + m)
+    p = synth.random_problem(rng, n, m)
+    st, y = _run(pa, ctx, p, flags)
+    assert st == pa.PA_OK, pa.pa_strerror(st)
+    ref = oracle.hash_words(p.seed, n, m, p.key)
+    assert np.array_equal(y, ref), describe(y, ref, m)
+    s = pa.pa_last_stats(ctx)
+    assert s["max_residual"] <= 0.125
+
+
+@pytest.mark.parametrize("cap,n,m", [(12, 20_000, 900), (12, 9000, 20_000), (13, 50_000, 30_000),
+                                     (12, 4096, 1), (12, 1, 5000), (14, 200_003, 100_001)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_forced_tiling(pa, ctx, cap, n, m, prec, monkeypatch):
+    """Key chunks (Eq. 4-6) and output windows at small sizes by capping the
+    FFT length class."""
+    from gpu_util import describe
+    monkeypatch.setenv("PA_MAX_LOG2_LEN", str(cap))
+    flags = pa.PA_PREC_FP64 if prec == "fp64" else pa.PA_PREC_FP32_SEG
+    plan = pa.pa_plan_query(n, m, flags)
+    rng = np.random.default_rng(cap * 7 + n + 3 * m)
+    p = synth.random_problem(rng, n, m)
+    st, y = _run(pa, ctx, p, flags)
+    assert st == pa.PA_OK, pa.pa_strerror(st)
+    ref = oracle.hash_words(p.seed, n, m, p.key)
+    assert np.array_equal(y, ref), describe(y, ref, m) + f" plan {plan}"
+    s = pa.pa_last_stats(ctx)
+    assert s["tiles"] == plan["chunks"] * plan["windows"]
+    assert plan["log2_len"] <= cap
+
+
+def _digest(words):
+    return hashlib.sha256(np.ascontiguousarray(words, dtype="<u8").tobytes()).hexdigest()
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+@pytest.mark.parametrize("prec", ["fp64", "auto"])
+def test_configs_golden(pa, ctx, name, prec):
+    flags = pa.PA_PREC_FP64 if prec == "fp64" else pa.PA_PREC_AUTO
+    p = synth.single_config(name)
+    st, y = _run(pa, ctx, p, flags)
+    assert st == pa.PA_OK, pa.pa_strerror(st)
+    g = GOLDEN[name]
+    assert _digest(y) == g["sha256"], f"{name} {prec}: weight {int(np.unpackbits(y.view(np.uint8)).sum())} vs {g['weight']}"
+    s = pa.pa_last_stats(ctx)
+    print(name, prec, s, flush=True)
+
+
+def test_c1_vs_oracle(pa, ctx):
+    from gpu_util import describe
+    p = synth.single_config("c1")
+    st, y = _run(pa, ctx, p, pa.PA_PREC_FP64)
+    assert st == pa.PA_OK
+    ref = oracle.hash_words(p.seed, p.n, p.m, p.key)
+    assert np.array_equal(y, ref), describe(y, ref, p.m)
+
+
+def test_host_pointers(pa, ctx):
+    rng = np.random.default_rng(77)
+    p = synth.random_problem(rng, 30_000, 7000)
+    out = np.zeros(synth.words_for(p.m), np.uint64)
+    st = pa.pa_hash(ctx, p.seed, p.n, p.m, p.key, out, pa.PA_PREC_AUTO)
+    assert st == pa.PA_OK
+    assert np.array_equal(out, oracle.hash_words(p.seed, p.n, p.m, p.key))
+
+
+def test_invalid_arguments(pa, ctx):
+    from gpu_util import to_dev, empty_dev
+    s = to_dev(np.zeros(4, np.uint64))
+    k = to_dev(np.zeros(4, np.uint64))
+    o = empty_dev(4)
+    assert pa.pa_hash(ctx, s, 0, 5, k, o, 0) == pa.PA_EINVAL
+    assert pa.pa_hash(ctx, s, 5, 0, k, o, 0) == pa.PA_EINVAL
+    assert pa.pa_hash(ctx, 0, 5, 5, k, o, pa.PA_DEVICE_PTRS) == pa.PA_EINVAL
+    assert pa.pa_hash(ctx, s, 5, 5, k, o, 0x00F0) == pa.PA_EINVAL
