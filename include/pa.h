@@ -2,16 +2,16 @@
  * libpa — Toeplitz-hash privacy amplification on AMD Instinct MI355X (gfx950).
  *
  * The operation (paper section 2.1, Eq. 1; section 2.3, steps 1-2; section 3,
- * Fig. 1-2, Eq. 4-6): for an n-bit key x and an (n+m-1)-bit seed s, the m x n
+ * Fig. 1-2, Eq. 4-7): for an n-bit key x and an (n+m-1)-bit seed s, the m x n
  * Toeplitz matrix over GF(2) has T[i][j] = s[i - j + n - 1], and the hash is
  *
  *     y_i = XOR_{j<n} ( s[i - j + n - 1] AND x_j ),   0 <= i < m.
  *
  * y is the window [n-1, n+m-1) of the polynomial product s(z) x(z) reduced mod
  * 2 (section 3, step 3: outputs n .. n+m-1 of the product, counted from 1;
- * Eq. 6: mod-2 addition).  The library evaluates it as an exact FFT convolution
+ * Eq. 7: mod-2 addition).  The library evaluates it as an exact FFT convolution
  * (integer rounding, parity, output window), splitting long keys into chunks
- * and long outputs into windows whose partial hashes are XOR-merged (Eq. 4-6).
+ * and long outputs into windows whose partial hashes are XOR-merged (Eq. 4-7).
  *
  * Bit strings: arrays of uint64_t words, LSB-first: bit k of a string is
  * (w[k >> 6] >> (k & 63)) & 1.  A k-bit string occupies ceil(k/64) words.

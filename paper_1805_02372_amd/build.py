@@ -33,7 +33,7 @@ def _hipcc():
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *FLAGS]
+    cmd = [_hipcc(), *FLAGS, *os.environ.get("PA_EXTRA_HIPCC_FLAGS", "").split()]
     if src.endswith(".cpp"):
         cmd += ["-x", "hip"]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]

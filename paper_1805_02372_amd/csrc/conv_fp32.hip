@@ -1,13 +1,18 @@
-// FFT length classes for FP32 tiles: L = n1 * n2 = 2^logL, n2 = 2^max(logL-13, min(10, logL/2)),
-// 8 columns per pass-1 workgroup (64 B stores), 16 per pass-3 workgroup (128 B loads),
-// 16 points per thread.
+// FFT length classes for FP32 tiles.  2^12 .. 2^19: L = n1 * n2 with
+// n2 = 2^max(logL-13, min(10, logL/2)), workgroup-wide Stockham stages
+// (conv_kernels.hpp).  2^20 .. 2^24: n1 = 8192, n2 = L / 8192, wave-level transforms
+// (conv_v2.hpp).
 #include "conv_kernels.hpp"
+#include "conv_v2.hpp"
 
 namespace pa {
 
 #define PA_CLASS(LOGL, N1, N2) \
     {ClassCfg{32, LOGL, N1, N2, 8, 16, 16}, &ClassImpl<float, N1, N2, 8, 16, 16>::pass1, \
      &ClassImpl<float, N1, N2, 8, 16, 16>::pass2, &ClassImpl<float, N1, N2, 8, 16, 16>::pass3}
+#define PA_CLASS2(LOGL, N2) \
+    {ClassCfg{32, LOGL, kN1, N2, ClassImpl2<float, N2>::C1, ClassImpl2<float, N2>::C3, 16}, \
+     &ClassImpl2<float, N2>::pass1, &ClassImpl2<float, N2>::pass2, &ClassImpl2<float, N2>::pass3}
 
 static const ClassKernels kClasses32[] = {
     PA_CLASS(12, 64, 64),
@@ -18,11 +23,11 @@ static const ClassKernels kClasses32[] = {
     PA_CLASS(17, 512, 256),
     PA_CLASS(18, 512, 512),
     PA_CLASS(19, 1024, 512),
-    PA_CLASS(20, 1024, 1024),
-    PA_CLASS(21, 2048, 1024),
-    PA_CLASS(22, 4096, 1024),
-    PA_CLASS(23, 8192, 1024),
-    PA_CLASS(24, 8192, 2048),
+    PA_CLASS2(20, 128),
+    PA_CLASS2(21, 256),
+    PA_CLASS2(22, 512),
+    PA_CLASS2(23, 1024),
+    PA_CLASS2(24, 2048),
 };
 
 const ClassKernels* class_kernels32(int logL) {

@@ -2,10 +2,10 @@
 //
 // A tile convolves a seed slice w (bi+bo-1 bits, encoded +-1) with a key
 // chunk x (bi bits, encoded 0/1) circularly over L = n1*n2 >= bi+bo-1 points
-// and keeps outputs [bi-1, bi-1+bo) (paper section 3, step 3; Eq. 4-6).  The
+// and keeps outputs [bi-1, bi-1+bo) (paper section 3, step 3; Eq. 4-7).  The
 // key chunk is placed at circular offset -(bi-1), so the kept window starts at
 // index 0.  With the +-1 seed, z = w (*) x equals 2c - weight(x) on the window,
-// c being the 0/1 convolution, so bit = ((rint(z) + weight) / 2) mod 2 (Eq. 6).
+// c being the 0/1 convolution, so bit = ((rint(z) + weight) / 2) mod 2 (Eq. 7).
 //
 // Both sequences share one complex FFT: z_t = x_t + i w_t.  The length-L FFT
 // is split four-step, t = t1 + n1 t2, k = k2 + n2 k1:

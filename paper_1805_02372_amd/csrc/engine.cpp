@@ -93,25 +93,24 @@ pa_status Ctx::tables(int prec, int logL, Tables* out) {
         DevTables dt;
         size_t elt = prec == PREC_FP32 ? sizeof(float) : sizeof(double);
         std::vector<unsigned char> host;
-        size_t ntw, nfa, nfb;
+        size_t ntw, nfa, nfb, nst;
+        auto pack = [&](auto& th) {
+            ntw = th.tw.size(); nfa = th.fa.size(); nfb = th.fb.size(); nst = th.stw.size();
+            host.resize((ntw + nfa + nfb + nst) * elt);
+            memcpy(host.data(), th.tw.data(), ntw * elt);
+            memcpy(host.data() + ntw * elt, th.fa.data(), nfa * elt);
+            memcpy(host.data() + (ntw + nfa) * elt, th.fb.data(), nfb * elt);
+            memcpy(host.data() + (ntw + nfa + nfb) * elt, th.stw.data(), nst * elt);
+            dt.t.fshift = th.fshift;
+        };
         if (prec == PREC_FP32) {
             TableHost<float> th;
             build_tables<float>(logL, g.n1, g.n2, &th);
-            ntw = th.tw.size(); nfa = th.fa.size(); nfb = th.fb.size();
-            host.resize((ntw + nfa + nfb) * elt);
-            memcpy(host.data(), th.tw.data(), ntw * elt);
-            memcpy(host.data() + ntw * elt, th.fa.data(), nfa * elt);
-            memcpy(host.data() + (ntw + nfa) * elt, th.fb.data(), nfb * elt);
-            dt.t.fshift = th.fshift;
+            pack(th);
         } else {
             TableHost<double> th;
             build_tables<double>(logL, g.n1, g.n2, &th);
-            ntw = th.tw.size(); nfa = th.fa.size(); nfb = th.fb.size();
-            host.resize((ntw + nfa + nfb) * elt);
-            memcpy(host.data(), th.tw.data(), ntw * elt);
-            memcpy(host.data() + ntw * elt, th.fa.data(), nfa * elt);
-            memcpy(host.data() + (ntw + nfa) * elt, th.fb.data(), nfb * elt);
-            dt.t.fshift = th.fshift;
+            pack(th);
         }
         pa_status st = dt.buf.ensure(this, host.size());
         if (st != PA_OK) return st;
@@ -121,6 +120,7 @@ pa_status Ctx::tables(int prec, int logL, Tables* out) {
         dt.t.tw = base;
         dt.t.fa = base + ntw * elt;
         dt.t.fb = base + (ntw + nfa) * elt;
+        dt.t.stw = base + (ntw + nfa + nfb) * elt;
         it = tabs.emplace(key, dt).first;
     }
     *out = it->second.t;
@@ -493,9 +493,10 @@ pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, con
     }
     std::vector<JobDesc> jobs(1);
     fill_job(&jobs[0], dseed, dkey, dout, n, m, plan);
-    // Only an a-priori certified plan may skip the certificate read-back.
-    const bool async = dev && (flags & PA_ASYNC) && plan.prec == PREC_FP64;
+    // Only an a-priori certified plan may skip the certificate read-back;
+    // kernel timing needs the launch to finish.
     const bool timing = flags & PA_TIMING;
+    const bool async = dev && (flags & PA_ASYNC) && plan.prec == PREC_FP64 && !timing;
     pa_status s = ln.launch(c, plan.prec, plan.logL, jobs, timing, !async, &st);
     if (s == PA_OK && !async) s = ln.finish(c, flags, &st, nullptr);
     if (s == PA_OK && !dev) {

@@ -1,4 +1,4 @@
-// XOR merge of per-chunk partial hashes (paper Eq. 4-6: the final key is the
+// XOR merge of per-chunk partial hashes (paper Eq. 4-7: the final key is the
 // mod-2 sum of the intermediate keys of all blocks and batches).  Job j with
 // nchunks > 1 has nchunks stage rows of out_words words; out[w] = XOR over the
 // rows.  The rows already hold zeros beyond m, so no masking is needed.

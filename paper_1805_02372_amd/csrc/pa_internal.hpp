@@ -12,7 +12,7 @@ namespace pa {
 // Tile (b, o) with chunk start j0, length bi, window start i0, length bo uses
 // seed bits [sigma, sigma+bi+bo-1) with sigma = i0 - j0 + n - bi: by the
 // constant diagonals of T its outputs are the window [bi-1, bi-1+bo) of the
-// convolution of that seed slice with the key chunk (Eq. 4-6, Fig. 1-2).
+// convolution of that seed slice with the key chunk (Eq. 4-7, Fig. 1-2).
 struct JobDesc {
     const uint64_t* key;
     const uint64_t* seed;
@@ -58,6 +58,7 @@ struct Tables {
     const void* fa;       // w_L^{h << fshift}, h < L >> fshift
     const void* fb;       // w_L^l, l < 1 << fshift
     int fshift;
+    const void* stw;      // wave-transform stage tables, sizes 16..1024
 };
 
 typedef int (*launch_fn)(const JobTable& jt, void* ws, uint32_t* part, TileMeta* meta,

@@ -20,7 +20,16 @@ uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 uint64_t round_up64(uint64_t a) { return (a + 63) & ~uint64_t(63); }
 }  // namespace
 
-int min_logL(int) { return 12; }
+// Smallest class; PA_MIN_LOG2_LEN (12..24) raises it (with PA_MAX_LOG2_LEN it
+// pins the class, e.g. to exercise one kernel family).
+int min_logL(int) {
+    int lo = 12;
+    if (const char* e = getenv("PA_MIN_LOG2_LEN")) {
+        int v = atoi(e);
+        if (v > lo && v <= 24) lo = v;
+    }
+    return lo;
+}
 
 // Largest class; PA_MAX_LOG2_LEN (12..24) lowers it, e.g. to force key
 // chunking and output windows on small inputs.
@@ -36,15 +45,28 @@ int max_logL(int prec) {
 
 bool class_geometry(int prec, int logL, ClassGeom* g) {
     if (logL < 12 || logL > 24) return false;
-    int n2cap = prec == PREC_FP64 ? 11 : 10;
-    int n2log = std::max(logL - 13, std::min(n2cap, logL / 2));
     g->prec = prec;
     g->logL = logL;
+    g->r = 16;
+    if (logL >= 20) {  // wave-level classes: rows of 8192
+        const int n2 = 1 << (logL - 13);
+        const bool f32 = prec != PREC_FP64;
+        const int w = n2 > 1024 ? n2 / 1024 : 1, m = n2 > 1024 ? 1024 : n2;
+        const int waves1 = (f32 && w > 1) ? 16 : 8;
+        const int g3 = 1024 / (n2 / 2);
+        const int waves3 = (f32 && g3 == 1) ? 16 : 8;
+        g->n1 = 8192;
+        g->n2 = n2;
+        g->b1 = waves1 * (1024 / m) / w;
+        g->b3 = waves3 * g3;
+        return true;
+    }
+    int n2cap = prec == PREC_FP64 ? 11 : 10;
+    int n2log = std::max(logL - 13, std::min(n2cap, logL / 2));
     g->n2 = 1 << n2log;
     g->n1 = 1 << (logL - n2log);
     g->b1 = prec == PREC_FP64 ? 4 : 8;
     g->b3 = prec == PREC_FP64 ? 8 : 16;
-    g->r = 16;
     return true;
 }
 
@@ -99,7 +121,10 @@ bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& 
     bool found = false;
     const uint64_t max_outs = std::min<uint64_t>(ceil_div(m, 64), 1u << 14);
     uint64_t last_bo = 0;
+    const uint64_t min_chunks = ceil_div(n, std::min<uint64_t>(L, bi_cap == 0 ? 1 : bi_cap));
     for (uint64_t w = 1; w <= std::max<uint64_t>(1, max_outs); ++w) {
+        // every later candidate has >= w windows and >= min_chunks chunks
+        if (found && w * min_chunks >= best.tiles()) break;
         uint64_t Bo = (w == 1) ? m : round_up64(ceil_div(m, w));
         if (Bo == last_bo) continue;
         last_bo = Bo;

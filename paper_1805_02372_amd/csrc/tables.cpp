@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "tables.hpp"
+#include "wave_fft.hpp"
 
 namespace pa {
 
@@ -47,6 +48,21 @@ void build_tables(int logL, int n1, int n2, TableHost<T>* th) {
     roots(th->tw, NT, NT, 1);
     roots(th->fa, L >> th->fshift, L, 1ull << th->fshift);
     roots(th->fb, 1ull << th->fshift, L, 1);
+    // stage tables: size M, stage span Ns (> 1), radix 16: entry [k][r] = w_{16 Ns}^{k r}
+    th->stw.assign(2 * (size_t)wfft_tables_total(), T(0));
+    for (int lg = kWfftMinLog; lg <= kWfftMaxLog; ++lg) {
+        const int M = 1 << lg;
+        for (int ns = wfft_first_radix(M); ns < M; ns *= 16) {
+            const size_t base = (size_t)wfft_size_offset(M) + wfft_stage_offset(M, ns);
+            for (int k = 0; k < ns; ++k)
+                for (int r = 0; r < 16; ++r) {
+                    long double c, sn;
+                    unit_root((uint64_t)k * r, (uint64_t)ns * 16, &c, &sn);
+                    th->stw[2 * (base + k * 16 + r)] = (T)c;
+                    th->stw[2 * (base + k * 16 + r) + 1] = (T)sn;
+                }
+        }
+    }
 }
 
 template void build_tables<float>(int, int, int, TableHost<float>*);

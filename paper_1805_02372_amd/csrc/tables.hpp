@@ -11,8 +11,10 @@ void unit_root(uint64_t e, uint64_t N, long double* c, long double* s);
 // Interleaved (re, im) tables of one FFT length class:
 //   tw[e] = w_NT^e, e < NT = max(n1, n2);
 //   fa[h] = w_L^{h << fshift}, fb[l] = w_L^l, so w_L^e = fa[e >> fshift] fb[e & mask].
+//   stw: stage tables of the wave transforms of every size 16..1024 (layout
+//        in wave_fft.hpp).
 template <typename T> struct TableHost {
-    std::vector<T> tw, fa, fb;
+    std::vector<T> tw, fa, fb, stw;
     int fshift = 0;
 };
 

@@ -1,0 +1,127 @@
+// Wave-level FFTs for gfx950: one 64-lane wavefront transforms G independent
+// sequences of M points (M * G = 1024, 16 points per lane) in registers,
+// exchanging between Stockham stages through a wave-private LDS region.  A
+// wavefront executes its LDS operations in order, so the exchanges need no
+// workgroup barrier, only compiler ordering (wave_sync).
+//
+// Register layout: lane = g * (M/16) + j; register i holds element
+// j + i * (M/16) of transform g, before and after the transform.
+//
+// Stage twiddles come from per-stage tables laid out lane-major: for a stage
+// of radix Rs and span Ns (Ns > 1), entry [k][r] (k < Ns, r < 16) holds
+// w_{Ns Rs}^{k r} (forward root; zero for r >= Rs), so a lane's twiddles for
+// one butterfly are 16 consecutive entries (wide, contiguous loads).
+#pragma once
+#include "fft_core.hpp"
+
+namespace pa {
+
+// Returns p unchanged, but the compiler cannot see through it: loads through
+// the result cannot be hoisted above this point (keeps each stage's twiddle
+// loads next to their use instead of all of them live at once).
+template <typename P> __device__ __forceinline__ P opaque(P p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- stage tables (shared by host table builder and kernels)
+constexpr int wfft_first_radix(int M) {
+    int k = ilog2(M);
+    return (k % 4) ? (1 << (k % 4)) : 16;
+}
+// Entries of the stage tables of one M (all stages with Ns > 1).
+constexpr int wfft_table_size(int M) {
+    int total = 0;
+    int ns = wfft_first_radix(M);
+    while (ns < M) {
+        total += ns * 16;
+        ns *= 16;
+    }
+    return total;
+}
+// Offset of stage Ns of transform size M within the size-M tables.
+constexpr int wfft_stage_offset(int M, int Ns) {
+    int off = 0;
+    int ns = wfft_first_radix(M);
+    while (ns < Ns) {
+        off += ns * 16;
+        ns *= 16;
+    }
+    return off;
+}
+constexpr int kWfftMinLog = 4, kWfftMaxLog = 10;
+// Offset of the size-M tables within the table of all sizes 16..1024.
+constexpr int wfft_size_offset(int M) {
+    int off = 0;
+    for (int lg = kWfftMinLog; (1 << lg) < M; ++lg) off += wfft_table_size(1 << lg);
+    return off;
+}
+constexpr int wfft_tables_total() { return wfft_size_offset(1 << (kWfftMaxLog + 1)); }
+
+// LDS slots of one wave region (1024 points, one pad slot per 16).
+constexpr int kWaveSlots = 1024 + 64;
+__device__ __forceinline__ int wslot(int e) { return e + (e >> 4); }
+
+template <typename T, int DIR, int M, int Rs, int Ns>
+__device__ __forceinline__ void wfft_stage(cx<T> (&v)[16], cx<T>* __restrict__ reg, int j,
+                                           const cx<T>* __restrict__ stw) {
+    constexpr int R = 16, P = R / Rs, NR = M / R;
+    constexpr bool LAST = (Ns * Rs == M);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int q = j + p * NR;
+        const int k = q & (Ns - 1);
+        cx<T> u[Rs];
+#pragma unroll
+        for (int r = 0; r < Rs; ++r) u[r] = v[p + r * P];
+        if constexpr (Ns > 1) {
+            const cx<T>* __restrict__ tk = opaque(stw) + wfft_size_offset(M) + wfft_stage_offset(M, Ns) + k * 16;
+#pragma unroll
+            for (int r = 1; r < Rs; ++r) u[r] = twmul<DIR>(u[r], tk[r]);
+        }
+        dft<Rs, DIR>(u);
+#pragma unroll
+        for (int r = 0; r < Rs; ++r) v[p + r * P] = u[r];
+    }
+    if constexpr (!LAST) {
+        wave_sync();
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int q = j + p * NR;
+            const int k = q & (Ns - 1);
+            const int base = (q / Ns) * Ns * Rs + k;
+#pragma unroll
+            for (int r = 0; r < Rs; ++r) reg[wslot(base + r * Ns)] = v[p + r * P];
+        }
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = reg[wslot(j + i * NR)];
+        wave_sync();
+    }
+}
+
+template <typename T, int DIR, int M, int Ns>
+__device__ __forceinline__ void wfft_stages(cx<T> (&v)[16], cx<T>* __restrict__ reg, int j,
+                                            const cx<T>* __restrict__ stw) {
+    constexpr int Rs = (Ns == 1) ? wfft_first_radix(M) : 16;
+    wfft_stage<T, DIR, M, Rs, Ns>(v, reg, j, stw);
+    if constexpr (Ns * Rs < M) wfft_stages<T, DIR, M, Ns * Rs>(v, reg, j, stw);
+}
+
+// M-point transform of the values held by the M/16 lanes of one transform
+// group; `reg` is that group's private LDS region (>= M + M/16 slots), `j` the
+// lane within the group, `stw` the base of the stage tables of all sizes.
+template <typename T, int DIR, int M>
+__device__ __forceinline__ void wave_fft(cx<T> (&v)[16], cx<T>* __restrict__ reg, int j,
+                                         const cx<T>* __restrict__ stw) {
+    static_assert(M >= 16 && M <= 1024 && (M & (M - 1)) == 0, "wave transform size");
+    wfft_stages<T, DIR, M, 1>(v, reg, j, stw);
+}
+
+}  // namespace pa

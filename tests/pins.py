@@ -16,7 +16,7 @@ What fixes each check:
   unit keys.
 * ``pin_convolve``: section 3, step 3 computes the hash as a polynomial
   product (FFT, product, inverse FFT) and keeps outputs n .. n+l-1 (1-based),
-  then reduces mod 2 (Eq. 6).  np.convolve is the library convolution; its
+  then reduces mod 2 (Eq. 7).  np.convolve is the library convolution; its
   window [n-1, n+m-1) mod 2 must equal the hash.
 * ``pin_clmul``: the same window of the carry-less (GF(2)[z]) product of the
   two bit strings, computed with Python integer shifts and XORs.
@@ -24,7 +24,7 @@ What fixes each check:
   parity of the key's weight; all-ones key -> y_i is the parity of
   s[i .. i+n-1]; unit key e_j -> column j = s[n-1-j .. n-1-j+m).
 * ``pin_linearity``: T(x xor z) = Tx xor Tz.
-* ``pin_block_split``: paper Eq. 4-6 (split the key into blocks, hash each
+* ``pin_block_split``: paper Eq. 4-7 (split the key into blocks, hash each
   block with its slice of T, XOR the intermediate keys) and the output split
   (the matrix columns "may also need to be divided", section 3).
 * ``pin_universal``: every nonzero difference d is mapped to 0 by exactly
@@ -138,7 +138,7 @@ def pin_block_split(H, shapes=((10, 4), (100, 30), (129, 65))):
             n2 = n - n1
             a = H(s[n2:n2 + n1 + m - 1], n1, m, x[:n1])
             b = H(s[:n2 + m - 1], n2, m, x[n1:])
-            _eq(full, a ^ b, f"Eq.4-6 key split n1={n1} (n={n}, m={m})")
+            _eq(full, a ^ b, f"Eq.4-7 key split n1={n1} (n={n}, m={m})")
         for lo, hi in [(0, 1), (1, m), (m // 2, m)]:
             if hi <= lo:
                 continue

@@ -59,7 +59,7 @@ def test_small_shapes(pa, ctx, prec, n, m):
                                      (12, 4096, 1), (12, 1, 5000), (14, 200_003, 100_001)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_forced_tiling(pa, ctx, cap, n, m, prec, monkeypatch):
-    """Key chunks (Eq. 4-6) and output windows at small sizes by capping the
+    """Key chunks (Eq. 4-7) and output windows at small sizes by capping the
     FFT length class."""
     from gpu_util import describe
     monkeypatch.setenv("PA_MAX_LOG2_LEN", str(cap))
@@ -74,6 +74,41 @@ def test_forced_tiling(pa, ctx, cap, n, m, prec, monkeypatch):
     s = pa.pa_last_stats(ctx)
     assert s["tiles"] == plan["chunks"] * plan["windows"]
     assert plan["log2_len"] <= cap
+
+
+# Long classes (2^20..2^24, rows of 8192, wave-level transforms): key chunks,
+# output windows and the two-wave column split of n2 = 2048, pinned by the
+# class bounds.
+LONG = [(20, 20, 2_000_003, 600_001), (20, 20, 300_000, 1_500_000), (21, 21, 1_500_000, 1_000_000),
+        (22, 22, 3_000_000, 700_000), (23, 23, 5_000_000, 2_000_000), (24, 24, 9_000_000, 3_000_000)]
+
+
+@pytest.mark.parametrize("lo,hi,n,m", LONG)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_long_classes(pa, ctx, lo, hi, n, m, prec, monkeypatch):
+    from gpu_util import describe
+    monkeypatch.setenv("PA_MIN_LOG2_LEN", str(lo))
+    monkeypatch.setenv("PA_MAX_LOG2_LEN", str(hi))
+    flags = pa.PA_PREC_FP64 if prec == "fp64" else pa.PA_PREC_FP32_SEG
+    plan = pa.pa_plan_query(n, m, flags)
+    assert plan["log2_len"] == hi
+    rng = np.random.default_rng(lo * 1000 + n % 997 + m % 991)
+    p = synth.random_problem(rng, n, m)
+    st, y = _run(pa, ctx, p, flags)
+    assert st == pa.PA_OK, pa.pa_strerror(st)
+    if n * m <= 3e12:  # full oracle (about n*m/64 word steps)
+        ref = oracle.hash_words(p.seed, n, m, p.key)
+        assert np.array_equal(y, ref), describe(y, ref, m) + f" plan {plan}"
+    else:  # sampled outputs, each by the word-parallel definition
+        idx = np.unique(np.concatenate([np.arange(64), np.arange(m - 64, m),
+                                        np.random.default_rng(5).integers(0, m, 4000)]))
+        ref = oracle.hash_select(p.seed, n, m, p.key, idx)
+        got = synth.bits_to_array(y, m)[idx]
+        assert np.array_equal(got, ref), f"{int((got != ref).sum())} sampled bits differ, plan {plan}"
+        assert int(y[-1]) >> (m % 64) == 0 if m % 64 else True
+    s = pa.pa_last_stats(ctx)
+    assert s["tiles"] == plan["chunks"] * plan["windows"]
+    print(prec, lo, n, m, "residual", s["max_residual"], flush=True)
 
 
 def _digest(words):
