@@ -40,14 +40,17 @@ pa_status DevBuf::ensure(Ctx* c, size_t need) {
     if (need <= bytes) return PA_OK;
     release(c);
     size_t want = std::max(need, (size_t)256);
-    if (c->used.load() + want > c->budget) return PA_ENOMEM;
+    uint64_t cur = c->used.load();
+    do {  // reserve against the budget
+        if (cur + want > c->budget) return PA_ENOMEM;
+    } while (!c->used.compare_exchange_weak(cur, cur + want));
     if (hipMalloc(&ptr, want) != hipSuccess) {
         ptr = nullptr;
+        c->used -= want;
         (void)hipGetLastError();
         return PA_ENOMEM;
     }
     bytes = want;
-    c->used += want;
     return PA_OK;
 }
 
@@ -91,7 +94,7 @@ pa_status Ctx::tables(int prec, int logL, Tables* out) {
         ClassGeom g;
         if (!class_geometry(prec, logL, &g)) return PA_EINVAL;
         DevTables dt;
-        size_t elt = prec == PREC_FP32 ? sizeof(float) : sizeof(double);
+        size_t elt = prec == PREC_FP64 ? sizeof(double) : sizeof(float);
         std::vector<unsigned char> host;
         size_t ntw, nfa, nfb, nst;
         auto pack = [&](auto& th) {
@@ -103,7 +106,12 @@ pa_status Ctx::tables(int prec, int logL, Tables* out) {
             memcpy(host.data() + (ntw + nfa + nfb) * elt, th.stw.data(), nst * elt);
             dt.t.fshift = th.fshift;
         };
-        if (prec == PREC_FP32) {
+        if (prec == PREC_NTT) {
+            elt = sizeof(uint32_t);
+            TableHost<uint32_t> th;
+            build_ntt_tables(logL, g.n1, g.n2, &th);
+            pack(th);
+        } else if (prec == PREC_FP32) {
             TableHost<float> th;
             build_tables<float>(logL, g.n1, g.n2, &th);
             pack(th);
@@ -242,14 +250,15 @@ pa_status Lane::launch(Ctx* c, int prec_, int logL_, std::vector<JobDesc>& js, b
     if (st != PA_OK) return st;
 
     // tiles per launch: as many as the budget allows, at least one
-    const size_t elt = cfg.prec == 32 ? 8 : 16;
+    const size_t elt = cfg.prec == 64 ? 16 : 8;
     const size_t tile_bytes = ((size_t)1 << cfg.logL) * elt;
     const size_t part_bytes = (size_t)(cfg.n1 / cfg.b1) * sizeof(uint32_t);
     size_t G = total;
     if (ws.bytes < G * tile_bytes || part.bytes < G * part_bytes) {
         const uint64_t u = c->used.load();
         const uint64_t mine = ws.bytes + part.bytes;
-        const uint64_t avail = c->budget > u ? c->budget - u + mine : mine;
+        uint64_t avail = c->budget > u ? c->budget - u + mine : mine;
+        if (cap) avail = std::min<uint64_t>(avail, cap);
         G = std::max<size_t>(1, std::min<size_t>(G, avail / (tile_bytes + part_bytes)));
     }
     st = ws.ensure(c, G * tile_bytes);
@@ -496,7 +505,7 @@ pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, con
     // Only an a-priori certified plan may skip the certificate read-back;
     // kernel timing needs the launch to finish.
     const bool timing = flags & PA_TIMING;
-    const bool async = dev && (flags & PA_ASYNC) && plan.prec == PREC_FP64 && !timing;
+    const bool async = dev && (flags & PA_ASYNC) && plan.prec != PREC_FP32 && !timing;
     pa_status s = ln.launch(c, plan.prec, plan.logL, jobs, timing, !async, &st);
     if (s == PA_OK && !async) s = ln.finish(c, flags, &st, nullptr);
     if (s == PA_OK && !dev) {

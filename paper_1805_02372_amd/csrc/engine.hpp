@@ -55,6 +55,7 @@ struct PassTimer {
 struct Lane {
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    uint64_t cap = 0;     // workspace cap in bytes (0: the context budget)
     DevBuf ws, part, meta, jobs_dev, stage, io;
     HostBuf meta_host, jobs_host;
     PassTimer timer;

@@ -30,10 +30,12 @@ int launch_merge(const JobTable& jt, uint64_t max_words, void* stream) {
 
 const ClassKernels* class_kernels32(int logL);
 const ClassKernels* class_kernels64(int logL);
+const ClassKernels* class_kernels_ntt(int logL);
 
 const ClassKernels* class_kernels(int prec, int logL) {
     if (prec == 32) return class_kernels32(logL);
     if (prec == 64) return class_kernels64(logL);
+    if (prec == 1) return class_kernels_ntt(logL);
     return nullptr;
 }
 

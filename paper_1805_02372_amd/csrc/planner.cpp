@@ -48,6 +48,14 @@ bool class_geometry(int prec, int logL, ClassGeom* g) {
     g->prec = prec;
     g->logL = logL;
     g->r = 16;
+    if (prec == PREC_NTT) {
+        const int n2log = std::min(11, logL / 2);
+        g->n2 = 1 << n2log;
+        g->n1 = 1 << (logL - n2log);
+        g->b1 = 4;
+        g->b3 = 8;
+        return true;
+    }
     if (logL >= 20) {  // wave-level classes: rows of 8192
         const int n2 = 1 << (logL - 13);
         const bool f32 = prec != PREC_FP64;

@@ -198,6 +198,7 @@ pa_status pa_submit(pa_ctx* ctx, uint32_t seed_id, uint64_t n, uint64_t m, const
         for (Lane& ln : lanes) {
             if (hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) != hipSuccess) return PA_EDEVICE;
             ln.own_stream = true;
+            ln.cap = c->budget / (lanes.size() + 1);  // each lane's share; the rest for seeds and direct calls
         }
         lk.lock();
         if (!c->worker_started) {

@@ -66,6 +66,41 @@ void build_tables(int logL, int n1, int n2, TableHost<T>* th) {
 }
 
 template void build_tables<float>(int, int, int, TableHost<float>*);
+
+namespace {
+constexpr uint64_t kP = 2013265921ull;  // 15 * 2^27 + 1
+uint64_t mulmod(uint64_t a, uint64_t b) { return (a * b) % kP; }
+uint64_t powmod(uint64_t a, uint64_t e) {
+    uint64_t r = 1;
+    a %= kP;
+    while (e) {
+        if (e & 1) r = mulmod(r, a);
+        a = mulmod(a, a);
+        e >>= 1;
+    }
+    return r;
+}
+uint32_t to_mont(uint64_t a) { return (uint32_t)(((a % kP) << 32) % kP); }
+}  // namespace
+
+void build_ntt_tables(int logL, int n1, int n2, TableHost<uint32_t>* th) {
+    const uint64_t L = 1ull << logL;
+    const uint64_t NT = (uint64_t)(n1 > n2 ? n1 : n2);
+    th->fshift = (logL + 1) / 2;
+    const uint64_t wNT = powmod(31, (kP - 1) / NT), wL = powmod(31, (kP - 1) / L);
+    th->tw.resize(NT);
+    uint64_t a = 1;
+    for (uint64_t e = 0; e < NT; ++e, a = mulmod(a, wNT)) th->tw[e] = to_mont(a);
+    const uint64_t nfa = L >> th->fshift, nfb = 1ull << th->fshift;
+    th->fa.resize(nfa);
+    th->fb.resize(nfb);
+    const uint64_t step = powmod(wL, nfb);
+    a = 1;
+    for (uint64_t h = 0; h < nfa; ++h, a = mulmod(a, step)) th->fa[h] = to_mont(a);
+    a = 1;
+    for (uint64_t l = 0; l < nfb; ++l, a = mulmod(a, wL)) th->fb[l] = to_mont(a);
+    th->stw = {(uint32_t)powmod(L, kP - 2), to_mont(1)};
+}
 template void build_tables<double>(int, int, int, TableHost<double>*);
 
 }  // namespace pa

@@ -20,4 +20,9 @@ template <typename T> struct TableHost {
 
 template <typename T> void build_tables(int logL, int n1, int n2, TableHost<T>* th);
 
+// Number-theoretic tables modulo p = 15 * 2^27 + 1 in Montgomery form
+// (a -> a 2^32 mod p): tw[e] = w_NT^e, fa / fb the two-level w_L tables, and
+// stw = {L^{-1} mod p (plain), 2^32 mod p}.  w_N = 31^((p-1)/N).
+void build_ntt_tables(int logL, int n1, int n2, TableHost<uint32_t>* th);
+
 }  // namespace pa

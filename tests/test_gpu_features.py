@@ -1,0 +1,250 @@
+"""Batching, serving, precision certificate/fallback and async paths on the
+GPU, each checked bit-exact against the CPU oracle (or its digests)."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "digests.json")))
+
+
+@pytest.fixture(scope="module")
+def pa():
+    from paper_1805_02372_amd import pa as _pa
+    return _pa
+
+
+@pytest.fixture(scope="module")
+def ctx(pa):
+    import torch
+    assert torch.cuda.is_available()
+    c = pa.pa_create(0, 0, None)
+    yield c
+    pa.pa_destroy(c)
+
+
+def _digest(words):
+    return hashlib.sha256(np.ascontiguousarray(words, dtype="<u8").tobytes()).hexdigest()
+
+
+def _dev_job(p):
+    from gpu_util import to_dev, empty_dev
+    return (to_dev(p.seed), to_dev(p.key), empty_dev(synth.words_for(p.m)), p.n, p.m)
+
+
+def _words(t, m):
+    from gpu_util import from_dev
+    return from_dev(t)[: synth.words_for(m)]
+
+
+# ------------------------------------------------------------------ batching
+
+def test_batch_64_jobs_vs_golden(pa, ctx):
+    """The 64-job batch workload in one batched launch, each job against its
+    oracle digest."""
+    import torch
+    jobs = synth.batch_jobs()
+    dev = [_dev_job(p) for p in jobs]
+    print("batch of", len(jobs), flush=True)
+    st, per = pa.pa_hash_batch(ctx, dev, pa.PA_PREC_AUTO)
+    torch.cuda.synchronize()
+    assert st == pa.PA_OK and all(s == pa.PA_OK for s in per)
+    stats = pa.pa_last_stats(ctx)
+    assert stats["tiles"] >= len(jobs)
+    for k, (p, d) in enumerate(zip(jobs, dev)):
+        assert _digest(_words(d[2], p.m)) == GOLDEN["c4"][k]["sha256"], f"job {k} n={p.n} m={p.m}"
+
+
+@pytest.mark.parametrize("flags", ["auto", "fp64"])
+def test_batch_equals_single_calls(pa, ctx, flags):
+    """pa_hash_batch(jobs)[k] == pa_hash(jobs[k]) bit for bit, uneven shapes."""
+    import torch
+    f = pa.PA_PREC_AUTO if flags == "auto" else pa.PA_PREC_FP64
+    rng = np.random.default_rng(11)
+    shapes = [(1, 1), (70, 3), (5000, 4999), (200_000, 10_000), (1_000_003, 300_001), (64, 64),
+              (33_333, 77_777)]
+    probs = [synth.random_problem(rng, n, m) for n, m in shapes]
+    dev = [_dev_job(p) for p in probs]
+    st, per = pa.pa_hash_batch(ctx, dev, f)
+    torch.cuda.synchronize()
+    assert st == pa.PA_OK, pa.pa_strerror(st)
+    for p, d in zip(probs, dev):
+        single = _dev_job(p)
+        assert pa.pa_hash(ctx, single[0], p.n, p.m, single[1], single[2], f) == pa.PA_OK
+        torch.cuda.synchronize()
+        yb, ys = _words(d[2], p.m), _words(single[2], p.m)
+        assert np.array_equal(yb, ys), (p.n, p.m)
+        if p.n * p.m < 5e11:
+            assert np.array_equal(yb, oracle.hash_words(p.seed, p.n, p.m, p.key)), (p.n, p.m)
+
+
+def test_batch_host_pointers(pa, ctx):
+    rng = np.random.default_rng(12)
+    probs = [synth.random_problem(rng, n, m) for n, m in [(1000, 200), (77, 1000), (300_000, 5000)]]
+    outs = [np.zeros(synth.words_for(p.m), np.uint64) for p in probs]
+    st, per = pa.pa_hash_batch(ctx, [(p.seed, p.key, o, p.n, p.m) for p, o in zip(probs, outs)],
+                               pa.PA_PREC_AUTO)
+    assert st == pa.PA_OK
+    for p, o in zip(probs, outs):
+        assert np.array_equal(o, oracle.hash_words(p.seed, p.n, p.m, p.key))
+
+
+def test_batch_invalid_job(pa, ctx):
+    rng = np.random.default_rng(13)
+    p = synth.random_problem(rng, 100, 10)
+    good = _dev_job(p)
+    bad = (good[0], good[1], good[2], 0, 10)
+    st, per = pa.pa_hash_batch(ctx, [good, bad], 0)
+    assert st == pa.PA_EINVAL and per == [pa.PA_OK, pa.PA_EINVAL]
+
+
+# --------------------------------------------------- precision certificate
+
+def test_fp32_certificate_falls_back_on_all_ones_seed(pa, ctx):
+    """An all-ones seed makes the +-1 encoded spectrum a huge DC term; FP32
+    tiles fail their certificate and are re-run in FP64.  Closed form: every
+    output is the parity of the key's weight."""
+    from gpu_util import gpu_hash
+    rng = np.random.default_rng(21)
+    n, m = 3_000_000, 100_000
+    seed = synth.pattern_bits("ones", n + m - 1)
+    key = synth.gen_bits(rng, n)
+    st, y = gpu_hash(pa, ctx, seed, n, m, key, pa.PA_PREC_FP32_SEG)
+    assert st == pa.PA_OK
+    s = pa.pa_last_stats(ctx)
+    assert s["fallback_tiles"] > 0, s
+    par = int(np.unpackbits(key.view(np.uint8)).sum()) & 1
+    assert np.array_equal(synth.bits_to_array(y, m), np.full(m, par, np.uint8))
+    st2, _ = gpu_hash(pa, ctx, seed, n, m, key, pa.PA_PREC_FP32_SEG | pa.PA_NO_FALLBACK)
+    assert st2 == pa.PA_EPRECISION
+
+
+@pytest.mark.parametrize("kind", ["period3", "block", "sparse"])
+def test_structured_inputs_exact(pa, ctx, kind):
+    """Structured seeds and keys (where FP32 error is largest) stay exact
+    under the certified plan, with or without fallback tiles."""
+    from gpu_util import gpu_hash, describe
+    n, m = 2_000_000, 250_000
+    seed = synth.pattern_bits(kind, n + m - 1)
+    key = synth.pattern_bits("period3" if kind != "period3" else "period2", n)
+    st, y = gpu_hash(pa, ctx, seed, n, m, key, pa.PA_PREC_AUTO)
+    assert st == pa.PA_OK
+    ref = oracle.hash_words(seed, n, m, key)
+    assert np.array_equal(y, ref), describe(y, ref, m)
+    print(kind, pa.pa_last_stats(ctx), flush=True)
+
+
+def test_async_fp64(pa, ctx):
+    import torch
+    rng = np.random.default_rng(31)
+    p = synth.random_problem(rng, 400_000, 90_000)
+    s, k, o, n, m = _dev_job(p)
+    st = pa.pa_hash(ctx, s, n, m, k, o, pa.PA_PREC_FP64 | pa.PA_ASYNC)
+    assert st == pa.PA_OK
+    torch.cuda.synchronize()   # the library stream is synchronised below by a later call
+    st = pa.pa_hash(ctx, s, n, m, k, o, pa.PA_PREC_FP64)   # synchronous call after it
+    assert st == pa.PA_OK
+    assert np.array_equal(_words(o, m), oracle.hash_words(p.seed, n, m, p.key))
+
+
+def test_timing_stats(pa, ctx):
+    rng = np.random.default_rng(32)
+    p = synth.random_problem(rng, 1_000_000, 100_000)
+    s, k, o, n, m = _dev_job(p)
+    assert pa.pa_hash(ctx, s, n, m, k, o, pa.PA_PREC_AUTO | pa.PA_TIMING) == pa.PA_OK
+    st = pa.pa_last_stats(ctx)
+    assert all(x > 0 for x in st["ms_pass"][:3]), st
+    assert st["model_bytes"] == st["tiles"] * 24 * (1 << st["log2_len"])
+
+
+# ------------------------------------------------------------------ serving
+
+def _serve(pa, ctx, reqs, seeds_dev, seed_ids):
+    from gpu_util import to_dev, empty_dev
+    bufs, tickets = [], []
+    for r in reqs:
+        kd = to_dev(r["key"])
+        od = empty_dev(synth.words_for(r["m"]))
+        st, t = pa.pa_submit(ctx, seed_ids[r["seed"]], r["n"], r["m"], kd, od)
+        assert st == pa.PA_OK, pa.pa_strerror(st)
+        bufs.append((kd, od))
+        tickets.append(t)
+    statuses = [pa.pa_wait(ctx, t) for t in tickets]
+    lat = [pa.pa_ticket_latency(ctx, t) for t in tickets]
+    outs = [_words(od, r["m"]) for (kd, od), r in zip(bufs, reqs)]
+    return statuses, outs, lat
+
+
+def _requests(rng, count, seed_bits, nmax=2_000_000):
+    reqs = []
+    for _ in range(count):
+        n = int(10 ** rng.uniform(3, np.log10(nmax)))
+        m = max(1, min(int(n * rng.uniform(0.02, 0.5)), seed_bits - n + 1))
+        reqs.append(dict(n=n, m=m, seed=int(rng.integers(0, 2)), key=synth.gen_bits(rng, n)))
+    return reqs
+
+
+def test_serving_mixed_stream_exact(pa, ctx):
+    """Requests submitted back to back are admitted as lanes free up and
+    batched together; each result equals the oracle and the same request run
+    alone."""
+    from gpu_util import to_dev, gpu_hash
+    rng = np.random.default_rng(41)
+    seed_bits = 3_000_000
+    seeds = [synth.gen_bits(rng, seed_bits) for _ in range(2)]
+    ids = [pa.pa_seed_register(ctx, to_dev(s), seed_bits) for s in seeds]
+    reqs = _requests(rng, 40, seed_bits)
+    statuses, outs, lat = _serve(pa, ctx, reqs, None, ids)
+    assert all(s == pa.PA_OK for s in statuses)
+    assert all(x > 0 for x in lat)
+    for r, y in zip(reqs, outs):
+        sw = seeds[r["seed"]]
+        st, alone = gpu_hash(pa, ctx, sw, r["n"], r["m"], r["key"], pa.PA_PREC_AUTO)
+        assert st == pa.PA_OK and np.array_equal(alone, y), (r["n"], r["m"])
+        if r["n"] * r["m"] < 3e11:
+            ref = oracle.hash_words(sw, r["n"], r["m"], r["key"])
+        else:
+            idx = np.random.default_rng(1).integers(0, r["m"], 2000)
+            ref_bits = oracle.hash_select(sw, r["n"], r["m"], r["key"], idx)
+            assert np.array_equal(synth.bits_to_array(y, r["m"])[idx], ref_bits)
+            continue
+        assert np.array_equal(y, ref), (r["n"], r["m"])
+
+
+def test_serving_tight_budget_admission(pa):
+    """With an HBM budget that fits only a few requests at a time, requests
+    wait for admission; none fails and all are exact."""
+    from gpu_util import to_dev
+    c = pa.pa_create(0, 192 << 20, None)
+    try:
+        rng = np.random.default_rng(42)
+        seed_bits = 2_500_000
+        seeds = [synth.gen_bits(rng, seed_bits) for _ in range(2)]
+        ids = [pa.pa_seed_register(c, to_dev(s), seed_bits) for s in seeds]
+        reqs = _requests(rng, 16, seed_bits, nmax=2_000_000)
+        statuses, outs, _ = _serve(pa, c, reqs, None, ids)
+        assert all(s == pa.PA_OK for s in statuses), statuses
+        for r, y in zip(reqs, outs):
+            if r["n"] * r["m"] < 3e11:
+                assert np.array_equal(y, oracle.hash_words(seeds[r["seed"]], r["n"], r["m"], r["key"]))
+    finally:
+        pa.pa_destroy(c)
+
+
+def test_serving_rejects_oversized_request(pa, ctx):
+    from gpu_util import to_dev, empty_dev
+    rng = np.random.default_rng(43)
+    sid = pa.pa_seed_register(ctx, to_dev(synth.gen_bits(rng, 1000)), 1000)
+    k = to_dev(synth.gen_bits(rng, 900))
+    o = empty_dev(4)
+    st, _ = pa.pa_submit(ctx, sid, 900, 200, k, o)   # needs 1099 seed bits
+    assert st == pa.PA_EINVAL
+    st, _ = pa.pa_submit(ctx, 12345, 10, 10, k, o)
+    assert st == pa.PA_EINVAL

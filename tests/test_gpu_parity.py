@@ -40,11 +40,16 @@ SMALL = [(1, 1), (1, 100), (100, 1), (2, 3), (63, 65), (64, 64), (65, 63), (1000
          (4097, 511), (5000, 5000), (100_000, 3000), (70_000, 70_001), (131_071, 1), (1, 131_071)]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "auto"])
+def _flags(pa, prec):
+    return {"fp64": pa.PA_PREC_FP64, "fp32": pa.PA_PREC_FP32_SEG, "auto": pa.PA_PREC_AUTO,
+            "ntt": pa.PA_PREC_NTT}[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "auto", "ntt"])
 @pytest.mark.parametrize("n,m", SMALL)
 def test_small_shapes(pa, ctx, prec, n, m):
     from gpu_util import describe
-    flags = {"fp64": pa.PA_PREC_FP64, "fp32": pa.PA_PREC_FP32_SEG, "auto": pa.PA_PREC_AUTO}[prec]
+    flags = _flags(pa, prec)
     rng = np.random.default_rng(n * 1000003 + m)
     p = synth.random_problem(rng, n, m)
     st, y = _run(pa, ctx, p, flags)
@@ -57,13 +62,13 @@ def test_small_shapes(pa, ctx, prec, n, m):
 
 @pytest.mark.parametrize("cap,n,m", [(12, 20_000, 900), (12, 9000, 20_000), (13, 50_000, 30_000),
                                      (12, 4096, 1), (12, 1, 5000), (14, 200_003, 100_001)])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "ntt"])
 def test_forced_tiling(pa, ctx, cap, n, m, prec, monkeypatch):
     """Key chunks (Eq. 4-7) and output windows at small sizes by capping the
     FFT length class."""
     from gpu_util import describe
     monkeypatch.setenv("PA_MAX_LOG2_LEN", str(cap))
-    flags = pa.PA_PREC_FP64 if prec == "fp64" else pa.PA_PREC_FP32_SEG
+    flags = _flags(pa, prec)
     plan = pa.pa_plan_query(n, m, flags)
     rng = np.random.default_rng(cap * 7 + n + 3 * m)
     p = synth.random_problem(rng, n, m)
@@ -84,12 +89,12 @@ LONG = [(20, 20, 2_000_003, 600_001), (20, 20, 300_000, 1_500_000), (21, 21, 1_5
 
 
 @pytest.mark.parametrize("lo,hi,n,m", LONG)
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "ntt"])
 def test_long_classes(pa, ctx, lo, hi, n, m, prec, monkeypatch):
     from gpu_util import describe
     monkeypatch.setenv("PA_MIN_LOG2_LEN", str(lo))
     monkeypatch.setenv("PA_MAX_LOG2_LEN", str(hi))
-    flags = pa.PA_PREC_FP64 if prec == "fp64" else pa.PA_PREC_FP32_SEG
+    flags = _flags(pa, prec)
     plan = pa.pa_plan_query(n, m, flags)
     assert plan["log2_len"] == hi
     rng = np.random.default_rng(lo * 1000 + n % 997 + m % 991)
@@ -116,9 +121,9 @@ def _digest(words):
 
 
 @pytest.mark.parametrize("name", ["c1", "c2", "c3"])
-@pytest.mark.parametrize("prec", ["fp64", "auto"])
+@pytest.mark.parametrize("prec", ["fp64", "auto", "ntt"])
 def test_configs_golden(pa, ctx, name, prec):
-    flags = pa.PA_PREC_FP64 if prec == "fp64" else pa.PA_PREC_AUTO
+    flags = _flags(pa, prec)
     p = synth.single_config(name)
     st, y = _run(pa, ctx, p, flags)
     assert st == pa.PA_OK, pa.pa_strerror(st)
