@@ -36,22 +36,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("conv_fp32.hip", "conv_fp64.hip", "conv_kernels.hpp", "conv_v2.hpp", "fft_core.hpp",
+                  "wave_fft.hpp", "merge.hip", "ntt.hip", "pa_internal.hpp")
+
+
 def kernel_source_digest() -> str:
+    """Digest of the device-code sources: HBM counters taken on other kernels
+    are not reported."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1805_02372_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def pass_bytes(prec_flag: int, log2_len: int, pa) -> list[float]:
-    """Algorithmic HBM bytes of one tile per pass: pass 1 writes the complex
-    array (e L), pass 2 reads it and writes half (1.5 e L), pass 3 reads the
-    half (0.5 e L); e = 8 (FP32) or 16 (FP64)."""
-    e = 16 if prec_flag == pa.PA_PREC_FP64 else 8
-    L = float(1 << log2_len)
-    return [e * L, 1.5 * e * L, 0.5 * e * L]
+def launch_bytes(st: dict, n: int, m: int) -> list[float]:
+    """Algorithmic HBM bytes of one launch of each pass over all tiles of a
+    job (e = 8 for FP32, 16 for FP64; L the FFT length; T tiles = C chunks x
+    W windows):
+      pass 1: reads each tile's key chunk and seed slice, writes the complex
+              array: e L T + (2 W n + C m) / 8
+      pass 2: reads the array, writes half of it: 1.5 e L T
+      pass 3: reads the half, writes each tile's output window: 0.5 e L T + C m / 8
+      merge:  reads the C partial hashes, writes the hash: (C + 1) m / 8 (C > 1)"""
+    e = 16 if st["prec"] == 0x20 else 8
+    L = float(1 << st["log2_len"])
+    C = -(-n // st["chunk_bits"])
+    W = -(-m // st["window_bits"])
+    T = C * W
+    merge = (C + 1) * m / 8 if C > 1 else 0.0
+    return [e * L * T + (2 * W * n + C * m) / 8, 1.5 * e * L * T, 0.5 * e * L * T + C * m / 8, merge]
 
 
 def run_single(pa, ctx, torch, prob, flags, steps, warmup):
@@ -108,6 +122,73 @@ def run_batch(pa, ctx, torch, jobs, flags, steps, warmup):
     return dict(elapsed=el, stats=pa.pa_last_stats(ctx), outs=outs)
 
 
+def run_serving(pa, ctx, torch, count: int, load: float = 0.7):
+    """Serving workload: `count` requests, n log-uniform in [1e5, 1e8], m/n
+    uniform in [0.02, 0.5], seeds = 8 resident 1.5e8-bit strings, Poisson
+    arrivals.  Request keys are prefixes of 8 resident random 1e8-bit
+    buffers (key k uses buffer k mod 8).  The arrival rate is `load` times the
+    capacity measured on a back-to-back burst of the same requests."""
+    import oracle
+    import synth
+    seeds, reqs = synth.serving_stream(count)
+    rng = np.random.default_rng(5)
+    keys = [synth.gen_bits(rng, 100_000_000) for _ in range(8)]
+    dseeds = [torch.from_numpy(sd.view(np.int64).copy()).to("cuda:0") for sd in seeds]
+    sids = [pa.pa_seed_register(ctx, d, 150_000_000) for d in dseeds]
+    del dseeds
+    dkeys = [torch.from_numpy(k.view(np.int64).copy()).to("cuda:0") for k in keys]
+    outs = [torch.empty(((r["m"] + 63) // 64,), dtype=torch.int64, device="cuda:0") for r in reqs]
+
+    def submit(k):
+        r = reqs[k]
+        st, t = pa.pa_submit(ctx, sids[r["seed_id"]], r["n"], r["m"], dkeys[k % 8], outs[k])
+        assert st == pa.PA_OK, pa.pa_strerror(st)
+        return t
+
+    # capacity on a burst of the first requests
+    burst = list(range(min(64, count)))
+    a = time.perf_counter()
+    tk = [submit(k) for k in burst]
+    for t in tk:
+        st = pa.pa_wait(ctx, t)
+        assert st == pa.PA_OK, pa.pa_strerror(st)
+    cap = sum(reqs[k]["n"] for k in burst) / (time.perf_counter() - a)
+    mean_n = float(np.mean([r["n"] for r in reqs]))
+    rate = load * cap / mean_n
+    scale = (reqs[-1]["t"] / len(reqs)) * rate   # synth arrivals are at 100/s; rescale
+    torch.cuda.synchronize()
+    log(f"[bench] serving: capacity {cap / 1e9:.2f} Gbps on a burst, arrival rate {rate:.0f}/s")
+    t0 = time.perf_counter()
+    tickets = []
+    for k, r in enumerate(reqs):
+        due = t0 + r["t"] / scale
+        while True:
+            dt = due - time.perf_counter()
+            if dt <= 0:
+                break
+            time.sleep(min(dt, 0.002))
+        tickets.append(submit(k))
+    status = [pa.pa_wait(ctx, t) for t in tickets]
+    wall = time.perf_counter() - t0
+    assert all(s == pa.PA_OK for s in status), [pa.pa_strerror(s) for s in set(status)]
+    lat = np.array([pa.pa_ticket_latency(ctx, t) for t in tickets])
+    # exactness spot check: 64 output bits of 8 requests, word-parallel oracle
+    chk = np.random.default_rng(6).choice(len(reqs), size=min(8, len(reqs)), replace=False)
+    exact = True
+    for k in chk:
+        r = reqs[int(k)]
+        idx = np.random.default_rng(int(k)).integers(0, r["m"], 64)
+        ref = oracle.hash_select(seeds[r["seed_id"]], r["n"], r["m"], keys[int(k) % 8], idx)
+        got = synth.bits_to_array(outs[int(k)].cpu().numpy().view(np.uint64), r["m"])[idx]
+        exact = exact and bool(np.array_equal(ref, got))
+    total_n = sum(r["n"] for r in reqs)
+    return {"requests": len(reqs), "sustained_gbps": round(total_n / wall / 1e9, 3),
+            "offered_rate_per_s": round(rate, 1), "burst_capacity_gbps": round(cap / 1e9, 3),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "wall_s": round(wall, 3), "spot_check_exact": exact}
+
+
 def cpu_baseline(prob, target_s: float = 12.0):
     """Oracle on a prefix of the outputs (full key): by the constant diagonals
     y[0:m'] is the hash with seed bits [0, n+m'-1) and m' outputs; its cost is
@@ -136,6 +217,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-job batch measurement")
+    ap.add_argument("--serve", type=int, default=2000, help="requests in the serving leg (0: skip)")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None, help="run one path only (profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 512 MiB device copy (HBM counter calibration under rocprofv3)")
@@ -183,6 +265,16 @@ def main():
         batch["gbps"] = sum(p.n for p in jobs) * bsteps / batch["elapsed"] / 1e9
         log(f"[bench] c4: {batch['gbps']:.2f} Gbps bit-exact={bexact}")
 
+    serving = None
+    if args.serve and not args.only:
+        log(f"[bench] serving leg, {args.serve} requests")
+        sctx = pa.pa_create(0, 32 << 30, None)   # a serving process of its own: 32 GiB budget
+        try:
+            serving = run_serving(pa, sctx, torch, args.serve)
+        finally:
+            pa.pa_destroy(sctx)
+        log(f"[bench] serving: {serving}")
+
     if args.calib_copy:
         a = torch.empty(512 << 20, dtype=torch.uint8, device="cuda:0")
         b = torch.empty_like(a)
@@ -194,11 +286,11 @@ def main():
     st = head["stats"]
     value = prob.n * args.steps / head["elapsed"] / 1e9
     # roofline of the dominant kernel
-    pb = pass_bytes(st["prec"], st["log2_len"], pa)
+    pb = launch_bytes(st, prob.n, prob.m)
     kms = head["kernel_ms"][:3]
     dom = int(np.argmax(kms))
     tiles = st["tiles"]
-    achieved = pb[dom] * tiles / (kms[dom] * 1e-3) / 1e9
+    achieved = pb[dom] / (kms[dom] * 1e-3) / 1e9
     traffic = None
     if os.path.exists(PROFILE_TRAFFIC):
         tr = json.load(open(PROFILE_TRAFFIC))
@@ -229,7 +321,7 @@ def main():
             "bound": "hbm", "kernel": f"pass{dom + 1}",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel_ms": round(kms[dom], 5),
+            "kernel_ms": round(kms[dom], 5), "bytes_per_launch": round(pb[dom]),
         },
         "pipeline": {
             "kernel_ms": [round(x, 5) for x in head["kernel_ms"]],
@@ -257,6 +349,8 @@ def main():
         line["batch_c4"] = {"jobs": 64, "gbps": round(batch["gbps"], 3), "tiles": batch["stats"]["tiles"],
                             "log2_len": batch["stats"]["log2_len"], "bit_exact": bool(batch["bit_exact"]),
                             "fallback_tiles": batch["stats"]["fallback_tiles"]}
+    if serving is not None:
+        line["serving_c5"] = serving
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(prob)

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -249,7 +250,14 @@ pa_status Lane::launch(Ctx* c, int prec_, int logL_, std::vector<JobDesc>& js, b
     st = meta.ensure(c, (size_t)total * sizeof(TileMeta));
     if (st != PA_OK) return st;
 
-    // tiles per launch: as many as the budget allows, at least one
+    if (js.size() > 1) {  // descriptors first: they are small but must fit
+        st = jobs_dev.ensure(c, js.size() * sizeof(JobDesc));
+        if (st != PA_OK) return st;
+        st = jobs_host.ensure(js.size() * sizeof(JobDesc));
+        if (st != PA_OK) return st;
+    }
+    // tiles per launch: as many as the budget (and the lane cap) allows; on a
+    // failed allocation halve until one tile
     const size_t elt = cfg.prec == 64 ? 16 : 8;
     const size_t tile_bytes = ((size_t)1 << cfg.logL) * elt;
     const size_t part_bytes = (size_t)(cfg.n1 / cfg.b1) * sizeof(uint32_t);
@@ -261,9 +269,12 @@ pa_status Lane::launch(Ctx* c, int prec_, int logL_, std::vector<JobDesc>& js, b
         if (cap) avail = std::min<uint64_t>(avail, cap);
         G = std::max<size_t>(1, std::min<size_t>(G, avail / (tile_bytes + part_bytes)));
     }
-    st = ws.ensure(c, G * tile_bytes);
-    if (st != PA_OK) return st;
-    st = part.ensure(c, G * part_bytes);
+    for (;;) {
+        st = ws.ensure(c, G * tile_bytes);
+        if (st == PA_OK) st = part.ensure(c, G * part_bytes);
+        if (st == PA_OK || G == 1) break;
+        G = (G + 1) / 2;
+    }
     if (st != PA_OK) return st;
 
     JobTable jt{};
@@ -271,10 +282,6 @@ pa_status Lane::launch(Ctx* c, int prec_, int logL_, std::vector<JobDesc>& js, b
         jt.one = js[0];
         jt.njobs = 0;
     } else {
-        st = jobs_dev.ensure(c, js.size() * sizeof(JobDesc));
-        if (st != PA_OK) return st;
-        st = jobs_host.ensure(js.size() * sizeof(JobDesc));
-        if (st != PA_OK) return st;
         memcpy(jobs_host.ptr, js.data(), js.size() * sizeof(JobDesc));
         if (hipMemcpyAsync(jobs_dev.ptr, jobs_host.ptr, js.size() * sizeof(JobDesc), hipMemcpyHostToDevice,
                            stream) != hipSuccess)
@@ -452,6 +459,7 @@ pa_status pa_create(pa_ctx** out, int device, uint64_t budget, void* hip_stream)
         c->main.own_stream = true;
     }
     c->serving_init();
+    if (const char* tc = getenv("PA_TUNE_CACHE")) (void)tune_load(c, tc);  // optional
     *out = reinterpret_cast<pa_ctx*>(c);
     return PA_OK;
 }

@@ -129,5 +129,7 @@ void fill_plan_stats(pa_stats* s, const TilePlan& p);
 void fill_job(JobDesc* jd, const uint64_t* seed, const uint64_t* key, uint64_t* out, uint64_t n, uint64_t m,
               const TilePlan& p);
 double now_seconds();
+pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path);
+pa_status tune_load(Ctx* c, const char* path);
 
 }  // namespace pa

@@ -194,6 +194,15 @@ pa_status pa_submit(pa_ctx* ctx, uint32_t seed_id, uint64_t n, uint64_t m, const
     if (!c->worker_started) {
         lk.unlock();
         if (hipSetDevice(c->device) != hipSuccess) return PA_EDEVICE;
+        {
+            // direct calls keep their workspace between calls; hand it back to
+            // the budget so that the serving lanes get their shares (it grows
+            // again on the next direct call)
+            std::lock_guard<std::mutex> g(c->mu);
+            c->main.ws.release(c);
+            c->main.part.release(c);
+            c->main.stage.release(c);
+        }
         std::vector<Lane> lanes(serve_lanes());
         for (Lane& ln : lanes) {
             if (hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) != hipSuccess) return PA_EDEVICE;

@@ -90,6 +90,8 @@ _sig = {
     "pa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "pa_plan_query": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(pa_plan)]),
     "pa_error_model": (ctypes.c_double, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64]),
+    "pa_tune": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_int, ctypes.c_char_p]),
+    "pa_tune_load": (ctypes.c_int, [_P, ctypes.c_char_p]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -213,6 +215,16 @@ def pa_plan_query(n: int, m: int, flags: int = 0) -> dict:
     p = pa_plan()
     _check(_lib.pa_plan_query(int(n), int(m), int(flags), ctypes.byref(p)), "pa_plan_query")
     return p.as_dict()
+
+
+def pa_tune(ctx, flags: int = 0, reps: int = 3, path: str | None = None) -> int:
+    """Measure per-tile class costs for this context's planner (and write them
+    to `path` as JSON when given).  Returns the status."""
+    return _lib.pa_tune(ctx, int(flags), int(reps), path.encode() if path else None)
+
+
+def pa_tune_load(ctx, path: str) -> int:
+    return _lib.pa_tune_load(ctx, path.encode())
 
 
 def pa_error_model(prec: int, log2_len: int, chunk_bits: int) -> float:

@@ -248,3 +248,24 @@ def test_serving_rejects_oversized_request(pa, ctx):
     assert st == pa.PA_EINVAL
     st, _ = pa.pa_submit(ctx, 12345, 10, 10, k, o)
     assert st == pa.PA_EINVAL
+
+
+# ------------------------------------------------------------------ tuning
+
+def test_tune_writes_and_loads(pa, ctx, tmp_path):
+    path = str(tmp_path / "tune.json")
+    assert pa.pa_tune(ctx, pa.PA_PREC_FP32_SEG, 1, path) == pa.PA_OK
+    data = json.load(open(path))
+    costs = [data["fp32"][str(k)] for k in range(12, 25)]
+    assert all(c > 0 for c in costs)
+    assert costs[-1] > costs[0]          # longer transforms cost more
+    c2 = pa.pa_create(0, 0, None)
+    try:
+        assert pa.pa_tune_load(c2, path) == pa.PA_OK
+        assert pa.pa_tune_load(c2, str(tmp_path / "missing.json")) == pa.PA_EINVAL
+        from gpu_util import gpu_hash
+        p = synth.random_problem(np.random.default_rng(3), 700_000, 123_457)
+        st, y = gpu_hash(pa, c2, p.seed, p.n, p.m, p.key, pa.PA_PREC_AUTO)
+        assert st == pa.PA_OK and np.array_equal(y, oracle.hash_words(p.seed, p.n, p.m, p.key))
+    finally:
+        pa.pa_destroy(c2)
