@@ -22,12 +22,6 @@ namespace pa {
 
 constexpr int kN1 = 8192;  // row length of the long classes
 
-// Occupancy request for the row pass (default: none, the compiler fits the
-// pair path without spills at two waves per SIMD).
-#ifndef PA_PASS2_OCCUPANCY
-#define PA_PASS2_OCCUPANCY
-#endif
-
 template <typename T, int N2> struct P1Geom {
     static constexpr int W = N2 > 1024 ? N2 / 1024 : 1;    // waves per column
     static constexpr int M = N2 > 1024 ? 1024 : N2;        // wave transform size
@@ -46,6 +40,16 @@ template <typename T, int N2> struct P3Geom {
     static constexpr int C = WAVES * G;
     static constexpr int THREADS = WAVES * 64;
     static constexpr int CW = (C + 31) / 32;               // 32-bit words per output row
+    static constexpr int SLOTS = (WAVES * kWaveSlots > M * C) ? WAVES * kWaveSlots : M * C;
+    // LDS with the stage tables and Hermitian twiddles copied in (the twiddles
+    // share space with the output bit array) vs without; copy them only when
+    // the workgroups per CU (160 KB of LDS) stay the same.
+    static constexpr size_t kBits = (size_t)N2 * CW * 4;
+    static constexpr size_t kHtw = (size_t)M * sizeof(cx<T>);
+    static constexpr size_t kBase = (size_t)SLOTS * sizeof(cx<T>) + C * sizeof(T) + 64;
+    static constexpr size_t kWithout = kBase + kBits;
+    static constexpr size_t kWith = kBase + (kBits > kHtw ? kBits : kHtw) + wfft_lds_entries(M) * sizeof(cx<T>);
+    static constexpr bool LDS_TAB = kWith <= 163840 && (163840 / kWith) >= (163840 / kWithout);
 };
 
 // Transposition tile: row k2 of C elements, columns XOR-swizzled by the row.
@@ -77,30 +81,59 @@ __device__ __forceinline__ uint64_t placed_key_bits(const uint64_t* __restrict__
     return part(u0, 0, fs) | part(0, fs, C - fs);
 }
 
+// ------------------------------------------------------------------ FP64 roots
+// Four-step twiddles are formed as FP64 products of two-level tables and
+// rounded once to the working precision: w_L^e = fa64[e >> fshift] fb64[e & mask].
+struct Root64 {
+    double re, im;
+};
+__device__ __forceinline__ Root64 mul64(Root64 a, Root64 b) {
+    return Root64{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ Root64 root64(const cx<double>* __restrict__ fa64, const cx<double>* __restrict__ fb64,
+                                         int fshift, uint32_t e) {
+    const cx<double> a = fa64[e >> fshift], b = fb64[e & ((1u << fshift) - 1u)];
+    return Root64{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __device__ __forceinline__ cx<T> rounded(Root64 w) { return cx<T>{(T)w.re, (T)w.im}; }
+
+// XCD-aware workgroup order: the hardware deals consecutive workgroups to the
+// 8 XCDs in turn; remap so that each XCD gets a contiguous range of logical
+// blocks (neighbouring column blocks of pass 1 share bit words in its L2).
+__device__ __forceinline__ uint32_t xcd_block() {
+    const uint32_t b = blockIdx.x, n = gridDim.x;
+    return (n & 7u) ? b : (b & 7u) * (n >> 3) + (b >> 3);
+}
+
 // ------------------------------------------------------------------ pass 1
 template <typename T, int N2>
 __global__ void __launch_bounds__((P1Geom<T, N2>::THREADS))
 k2_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const cx<T>* __restrict__ tw,
-         const cx<T>* __restrict__ fa, const cx<T>* __restrict__ fb, int fshift, const cx<T>* __restrict__ stw) {
+         const cx<T>* __restrict__ stw, const cx<double>* __restrict__ fa64, const cx<double>* __restrict__ fb64,
+         int fshift) {
     using Gm = P1Geom<T, N2>;
     constexpr int C = Gm::C, G = Gm::G, W = Gm::W, M = Gm::M, NJ = M / 16;
     constexpr uint32_t L = (uint32_t)kN1 * N2;
     constexpr int NCB = kN1 / C;
     constexpr int SLOTS = (Gm::WAVES * kWaveSlots > N2 * C) ? Gm::WAVES * kWaveSlots : N2 * C;
     static_assert(2 * N2 * sizeof(uint64_t) <= SLOTS * sizeof(cx<T>), "bit rows fit the LDS union");
+    static_assert(G * 16 * sizeof(Root64) <= kWaveSlots * sizeof(cx<T>), "twiddle factors fit a wave region");
     __shared__ __align__(16) cx<T> lds[SLOTS];
+    __shared__ __align__(16) cx<T> st[wfft_lds_entries(M)];
     __shared__ uint32_t wsum;
     uint64_t* kbits = reinterpret_cast<uint64_t*>(lds);   // consumed before the wave regions are used
     uint64_t* sbits = kbits + N2;
 
-    const uint32_t lt = blockIdx.x / NCB;
-    const uint32_t cb = blockIdx.x % NCB;
+    const uint32_t blk = xcd_block();
+    const uint32_t lt = blk / NCB;
+    const uint32_t cb = blk % NCB;
     const uint32_t t = jt.tile0 + lt;
     const JobDesc jd = find_job(jt, t);
     const TileGeo g = tile_geo(jd, t - jd.tile_begin);
     const int tid = threadIdx.x;
     const uint32_t bi = (uint32_t)g.bi, win = (uint32_t)(g.bi + g.bo - 1);
     if (tid == 0) wsum = 0;
+    wfft_load_lds<T, M>(st, stw, tid, Gm::THREADS);
     __syncthreads();
 
     // stage the bits of this workgroup's C columns: rows r = tid + q * THREADS
@@ -132,24 +165,40 @@ k2_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const
     __syncthreads();
 
     const int wv = tid >> 6, l = tid & 63;
-    cx<T> v[16];
-    int f, ka = 0, j;
+    int f, ka = 0, j, grp;
     if constexpr (W == 1) {
-        const int gg = l / NJ;
+        grp = l / NJ;
         j = l % NJ;
-        f = wv * G + gg;
+        f = wv * G + grp;
     } else {
         f = wv / W;
         ka = wv % W;
         j = l;
+        grp = 0;
     }
     const uint32_t t1 = cb * C + (uint32_t)f;
+    // Four-step twiddle w_L^{t1 k2} = base * c_i with
+    //   W = 1: k2 = j + NJ i,           base = w_L^{t1 j},          c_i = w_L^{NJ t1 i}
+    //   W = 2: k2 = 2 (j + 64 i) + ka,  base = w_L^{t1 (2 j + ka)}, c_i = w_L^{128 t1 i}
+    // Each lane fetches its share of its group's 16 factors now (latency hidden
+    // behind the transform); they are exchanged through LDS afterwards.
+    constexpr int LPG = W == 1 ? NJ : 64;            // lanes per transform group
+    constexpr int CPL = (16 + LPG - 1) / LPG;        // factors fetched per lane
+    constexpr uint32_t CSTEP = W == 1 ? (uint32_t)NJ : 128u;
+    const Root64 base = root64(fa64, fb64, fshift, W == 1 ? t1 * (uint32_t)j : t1 * (uint32_t)(2 * j + ka));
+    Root64 cf[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+        const int i = j + q * LPG;
+        cf[q] = root64(fa64, fb64, fshift, i < 16 ? CSTEP * t1 * (uint32_t)i : 0u);
+    }
     auto z = [&](int r) -> cx<T> {
         const T xb = (T)((kbits[r] >> f) & 1u);
         T wb = T(0);
         if (t1 + (uint32_t)kN1 * (uint32_t)r < win) wb = ((sbits[r] >> f) & 1u) ? T(1) : T(-1);
         return cx<T>{xb, wb};
     };
+    cx<T> v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int e = j + i * NJ;
@@ -163,17 +212,22 @@ k2_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const
         }
     }
     __syncthreads();  // bits consumed; LDS becomes wave regions
-    cx<T>* reg = lds + wv * kWaveSlots + (W == 1 ? (l / NJ) * (M + M / 16) : 0);
-    wave_fft<T, -1, M>(v, reg, j, stw);
+    cx<T>* reg = lds + wv * kWaveSlots + (W == 1 ? grp * (M + M / 16) : 0);
+    wave_fft_lds<T, -1, M>(v, reg, j, st);
 
-    // four-step twiddle, then transpose through LDS for row-segment stores
+    // exchange the factors through this wave's own region (its transform is done)
+    Root64* cw = reinterpret_cast<Root64*>(lds + wv * kWaveSlots) + grp * 16;
+    wave_sync();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int e = j + i * NJ;
-        const uint32_t k2 = (W == 1) ? (uint32_t)e : (uint32_t)(2 * e + ka);
-        v[i] = cmul(v[i], four_step_root(fa, fb, fshift, t1 * k2));
+    for (int q = 0; q < CPL; ++q) {
+        const int i = j + q * LPG;
+        if (i < 16) cw[i] = cf[q];
     }
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = cmul(v[i], rounded<T>(mul64(base, cw[i])));
     __syncthreads();
+    // transpose through LDS for row-segment stores
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int e = j + i * NJ;
@@ -199,50 +253,92 @@ k2_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const
 }
 
 // ------------------------------------------------------------------ pass 2
+// Shared memory of the row pass: the row exchange / wave regions, the stage
+// tables of the 1024-point transforms, and (FP32) the first-stage twiddles
+// t8[(ka-1) 1024 + nb] = w_8192^{ka nb}, ka = 1..7.  FP64 reads those from the
+// global table instead (its row region leaves no room): 156.7 KB vs 135.7 KB.
+template <typename T> struct RowSmem {
+    static constexpr bool kLds = sizeof(T) == 4;   // tables in LDS (FP32 only)
+    cx<T> data[8 * kWaveSlots];
+    cx<T> st[kLds ? wfft_lds_entries(1024) : 1];
+    cx<T> t8[kLds ? 7 * 1024 : 1];
+};
 
-// Forward transform of one 8192-point row.  Thread (wave w, lane l) ends with
-// X[8 k_b + w] in register i, k_b = l + 64 i.
 template <typename T>
-__device__ __forceinline__ void row_forward(const cx<T>* __restrict__ row, cx<T> (&X)[16], cx<T>* lds, int wv,
-                                            int l, const cx<T>* __restrict__ tw, const cx<T>* __restrict__ stw) {
-    constexpr int S = kWaveSlots;
-    cx<T> a[16];
+__device__ __forceinline__ void row_smem_load(RowSmem<T>& S, const cx<T>* __restrict__ tw,
+                                              const cx<T>* __restrict__ stw, int tid) {
+    if constexpr (RowSmem<T>::kLds) {
+        wfft_load_lds<T, 1024>(S.st, stw, tid, 512);
+        for (int e = tid; e < 7 * 1024; e += 512) S.t8[e] = tw[(1 + e / 1024) * (e % 1024)];
+    }
+}
+
+// 1024-point wave transform of the row pass, stage tables from LDS or global
+template <typename T, int DIR>
+__device__ __forceinline__ void row_wave_fft(cx<T> (&v)[16], cx<T>* __restrict__ reg, int l, const RowSmem<T>& S,
+                                             const cx<T>* __restrict__ stw) {
+    if constexpr (RowSmem<T>::kLds) wave_fft_lds<T, DIR, 1024>(v, reg, l, S.st);
+    else wave_fft<T, DIR, 1024>(v, reg, l, stw);
+}
+
+// w_8192^{ka nb}, 1 <= ka < 8, nb < 1024
+template <typename T>
+__device__ __forceinline__ cx<T> w8192(const RowSmem<T>& S, const cx<T>* __restrict__ tw, int ka, int nb) {
+    if constexpr (RowSmem<T>::kLds) return S.t8[(ka - 1) * 1024 + nb];
+    else return opaque(tw)[ka * nb];
+}
+
+template <typename T>
+__device__ __forceinline__ void row_load(cx<T> (&a)[16], const cx<T>* __restrict__ row, int wv, int l) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const int nb = wv * 64 + l + 512 * s;
 #pragma unroll
         for (int na = 0; na < 8; ++na) a[s * 8 + na] = row[nb + 1024 * na];
-        dft8<-1>(&a[s * 8]);
-        const cx<T>* __restrict__ tws = opaque(tw);
+    }
+}
+
+// Forward transform of one 8192-point row loaded by row_load (a is consumed).
+// Thread (wave w, lane l) ends with X[8 k_b + w] in register i, k_b = l + 64 i.
+template <typename T>
+__device__ __forceinline__ void row_forward(cx<T> (&a)[16], cx<T> (&X)[16], RowSmem<T>& S, int wv, int l,
+                                            const cx<T>* __restrict__ tw, const cx<T>* __restrict__ stw) {
+    constexpr int SS = kWaveSlots;
 #pragma unroll
-        for (int ka = 1; ka < 8; ++ka) a[s * 8 + ka] = cmul(a[s * 8 + ka], tws[nb * ka]);
+    for (int s = 0; s < 2; ++s) {
+        const int nb = wv * 64 + l + 512 * s;
+        dft8<-1>(&a[s * 8]);
+#pragma unroll
+        for (int ka = 1; ka < 8; ++ka) a[s * 8 + ka] = cmul(a[s * 8 + ka], w8192<T>(S, tw, ka, nb));
     }
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const int nb = wv * 64 + l + 512 * s;
 #pragma unroll
-        for (int ka = 0; ka < 8; ++ka) lds[ka * S + wslot(nb)] = a[s * 8 + ka];
+        for (int ka = 0; ka < 8; ++ka) S.data[ka * SS + wslot(nb)] = a[s * 8 + ka];
     }
     __syncthreads();
-    cx<T>* reg = lds + wv * S;
+    cx<T>* reg = S.data + wv * SS;
 #pragma unroll
     for (int i = 0; i < 16; ++i) X[i] = reg[wslot(l + 64 * i)];
     wave_sync();
-    wave_fft<T, -1, 1024>(X, reg, l, stw);
+    row_wave_fft<T, -1>(X, reg, l, S, stw);
 }
 
 // Inverse transform of a row held as P[8 k_b + w] (register i, k_b = l + 64 i);
 // returns a[t_b + 1024 t_a] in a[s * 8 + t_a] for t_b = w * 64 + l + 512 s.
 template <typename T>
-__device__ __forceinline__ void row_inverse(cx<T> (&P)[16], cx<T> (&a)[16], cx<T>* lds, int wv, int l,
+__device__ __forceinline__ void row_inverse(cx<T> (&P)[16], cx<T> (&a)[16], RowSmem<T>& S, int wv, int l,
                                             const cx<T>* __restrict__ tw, const cx<T>* __restrict__ stw) {
-    constexpr int S = kWaveSlots;
-    cx<T>* reg = lds + wv * S;
+    constexpr int SS = kWaveSlots;
+    cx<T>* reg = S.data + wv * SS;
     __syncthreads();  // every wave is done with its region
-    wave_fft<T, +1, 1024>(P, reg, l, stw);
+    row_wave_fft<T, +1>(P, reg, l, S, stw);
+    if (wv > 0) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) P[i] = cmulc(P[i], opaque(tw)[wv * (l + 64 * i)]);
+        for (int i = 0; i < 16; ++i) P[i] = cmulc(P[i], w8192<T>(S, tw, wv, l + 64 * i));
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 16; ++i) reg[wslot(l + 64 * i)] = P[i];
@@ -251,7 +347,7 @@ __device__ __forceinline__ void row_inverse(cx<T> (&P)[16], cx<T> (&a)[16], cx<T
     for (int s = 0; s < 2; ++s) {
         const int tb = wv * 64 + l + 512 * s;
 #pragma unroll
-        for (int ka = 0; ka < 8; ++ka) a[s * 8 + ka] = lds[ka * S + wslot(tb)];
+        for (int ka = 0; ka < 8; ++ka) a[s * 8 + ka] = S.data[ka * SS + wslot(tb)];
         dft8<+1>(&a[s * 8]);
     }
 }
@@ -274,73 +370,122 @@ __device__ __forceinline__ void row_mirror(cx<T> (&X)[16], cx<T>* lds, int wv, i
     }
 }
 
-template <typename T, int N2, int NCB1>
-__global__ void __launch_bounds__(512) PA_PASS2_OCCUPANCY
-k2_pass2(JobTable jt, cx<T>* __restrict__ ws, const uint32_t* __restrict__ part, TileMeta* __restrict__ meta,
-         const cx<T>* __restrict__ tw, const cx<T>* __restrict__ fa, const cx<T>* __restrict__ fb, int fshift,
-         const cx<T>* __restrict__ stw) {
-    constexpr uint32_t L = (uint32_t)kN1 * N2;
-    constexpr int NP = N2 / 2;
-    __shared__ __align__(16) cx<T> lds[8 * kWaveSlots];
-    __shared__ uint32_t wsum;
-
-    const uint32_t lt = blockIdx.x / NP;
-    const int pr = blockIdx.x % NP;
-    cx<T>* __restrict__ Y = ws + (size_t)lt * L;
-    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
-    const T quarter = T(0.25) / T(L);
-
-    if (pr == 0) {
-        // key-chunk weight from the pass-1 partial sums; reset the certificate
-        if (tid == 0) wsum = 0;
-        __syncthreads();
-        uint32_t s = 0;
-        for (int c = tid; c < NCB1; c += 512) s += part[(size_t)lt * NCB1 + c];
-        atomicAdd(&wsum, s);
-        __syncthreads();
-        if (tid == 0) meta[jt.tile0 + lt] = TileMeta{wsum, 0u, 0u, 0u};
-    }
-    // Workgroup pr > 0 owns the mirror pair of rows pr and n2-pr and produces
-    // V row pr.  Workgroup 0 owns rows 0 and n2/2, which are their own mirrors
-    // and whose V rows are real: row 0's goes to the real parts of row 0,
-    // row n2/2's to the real parts of row n2/2 (each row is read only by this
-    // workgroup, so storing in place is race-free).
-    if (pr != 0) {
-        cx<T> A[16], B[16], a[16];
-        row_forward<T>(Y + (size_t)pr * kN1, A, lds, wv, l, tw, stw);
-        row_forward<T>(Y + (size_t)(N2 - pr) * kN1, B, lds, wv, l, tw, stw);
-        row_mirror<T>(B, lds, wv, l, false);
-#pragma unroll
-        for (int i = 0; i < 16; ++i) A[i] = spectrum_product(A[i], B[i], quarter);
-        row_inverse<T>(A, a, lds, wv, l, tw, stw);
+// Store V row `row` (inverse four-step twiddle w_L^{-row t1}): t1 = x + 1024 ta
+// with x = w 64 + l + 512 s, so w_L^{row t1} = w_L^{row x} w_L^{1024 row ta},
+// an FP64 product rounded once.  `real`: keep the real part only.
+template <typename T>
+__device__ __forceinline__ void row_store(cx<T>* __restrict__ Yrow, cx<T> (&a)[16], uint32_t row, bool real,
+                                          int wv, int l, const cx<double>* __restrict__ fa64,
+                                          const cx<double>* __restrict__ fb64, int fshift) {
+    if constexpr (sizeof(T) == 8) {
+        // FP64 (register-bound): one table product per point
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int ta = 0; ta < 8; ++ta) {
                 const uint32_t t1 = (uint32_t)(wv * 64 + l + 512 * s + 1024 * ta);
-                Y[(size_t)pr * kN1 + t1] = cmulc(a[s * 8 + ta], four_step_root(fa, fb, fshift, (uint32_t)pr * t1));
+                cx<T> vv = cmulc(a[s * 8 + ta], rounded<T>(root64(fa64, fb64, fshift, row * t1)));
+                if (real) vv.im = T(0);
+                Yrow[t1] = vv;
             }
+        return;
+    }
+    Root64 b[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) b[s] = root64(fa64, fb64, fshift, row * (uint32_t)(wv * 64 + l + 512 * s));
+#pragma unroll
+    for (int ta = 0; ta < 8; ++ta) {
+        const Root64 c = root64(fa64, fb64, fshift, 1024u * row * (uint32_t)ta);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const uint32_t x = (uint32_t)(wv * 64 + l + 512 * s);
+            cx<T> vv = cmulc(a[s * 8 + ta], rounded<T>(mul64(b[s], c)));
+            if (real) vv.im = T(0);
+            Yrow[x + 1024u * (uint32_t)ta] = vv;
+        }
+    }
+}
+
+// Row pass over units: units 0 .. ntiles (n2/2 - 1) - 1 are mirror pairs (row
+// pr >= 1 with n2 - pr), the last ntiles units the self rows 0 and n2/2 of
+// each tile.  FP32 is persistent (workgroup b walks u = b, b + G, ..., G = one
+// workgroup per CU, tables loaded once); FP64 runs one unit per workgroup.
+template <typename T> constexpr bool kRowPersistent = sizeof(T) == 4;
+// One unit of the row pass.
+template <typename T, int N2, int NCB1>
+__device__ __forceinline__ void row_unit(uint32_t u, const JobTable& jt, cx<T>* __restrict__ ws,
+                                         const uint32_t* __restrict__ part, TileMeta* __restrict__ meta,
+                                         RowSmem<T>& S, uint32_t& wsum, const cx<T>* __restrict__ tw,
+                                         const cx<T>* __restrict__ stw, const cx<double>* __restrict__ fa64,
+                                         const cx<double>* __restrict__ fb64, int fshift) {
+    constexpr uint32_t L = (uint32_t)kN1 * N2;
+    constexpr int NP = N2 / 2;
+    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
+    const T quarter = T(0.25) / T(L);
+    const uint32_t npairs = jt.ntiles * (uint32_t)(NP - 1);
+    const bool pair = u < npairs;
+    const uint32_t lt = pair ? u / (uint32_t)(NP - 1) : u - npairs;
+    const uint32_t pr = pair ? 1u + u % (uint32_t)(NP - 1) : 0u;
+    cx<T>* __restrict__ Y = ws + (size_t)lt * L;
+    if (pair) {
+        // FP32 issues the second row's loads before the first transform;
+        // FP64 has no registers to spare for that
+        constexpr bool kHoist = sizeof(T) == 4;
+        cx<T> ra[16], rb[16], A[16], B[16], a[16];
+        row_load<T>(ra, Y + (size_t)pr * kN1, wv, l);
+        if constexpr (kHoist) row_load<T>(rb, Y + (size_t)(N2 - pr) * kN1, wv, l);
+        row_forward<T>(ra, A, S, wv, l, tw, stw);
+        if constexpr (!kHoist) row_load<T>(rb, Y + (size_t)(N2 - pr) * kN1, wv, l);
+        row_forward<T>(rb, B, S, wv, l, tw, stw);
+        row_mirror<T>(B, S.data, wv, l, false);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) A[i] = spectrum_product(A[i], B[i], quarter);
+        row_inverse<T>(A, a, S, wv, l, tw, stw);
+        row_store<T>(Y + (size_t)pr * kN1, a, pr, false, wv, l, fa64, fb64, fshift);
     } else {
+        // key-chunk weight from the pass-1 partial sums; reset the certificate
+        __syncthreads();
+        if (tid == 0) wsum = 0;
+        __syncthreads();
+        uint32_t sum = 0;
+        for (int c = tid; c < NCB1; c += 512) sum += part[(size_t)lt * NCB1 + c];
+        atomicAdd(&wsum, sum);
+        __syncthreads();
+        if (tid == 0) meta[jt.tile0 + lt] = TileMeta{wsum, 0u, 0u, 0u};
+        // rows 0 and n2/2 are their own mirrors and their V rows are real:
+        // each goes to the real parts of its own row
 #pragma nounroll
-        for (int u = 0; u < 2; ++u) {
-            const int row = u == 0 ? 0 : NP;
-            cx<T> A[16], B[16], a[16];
-            row_forward<T>(Y + (size_t)row * kN1, A, lds, wv, l, tw, stw);
+        for (int v = 0; v < 2; ++v) {
+            const uint32_t row = v == 0 ? 0u : (uint32_t)NP;
+            cx<T> ra[16], A[16], B[16], a[16];
+            row_load<T>(ra, Y + (size_t)row * kN1, wv, l);
+            row_forward<T>(ra, A, S, wv, l, tw, stw);
 #pragma unroll
             for (int i = 0; i < 16; ++i) B[i] = A[i];
-            row_mirror<T>(B, lds, wv, l, u == 0);
+            row_mirror<T>(B, S.data, wv, l, v == 0);
 #pragma unroll
             for (int i = 0; i < 16; ++i) A[i] = spectrum_product(A[i], B[i], quarter);
-            row_inverse<T>(A, a, lds, wv, l, tw, stw);
-#pragma unroll
-            for (int s = 0; s < 2; ++s)
-#pragma unroll
-                for (int ta = 0; ta < 8; ++ta) {
-                    const uint32_t t1 = (uint32_t)(wv * 64 + l + 512 * s + 1024 * ta);
-                    const cx<T> vv = cmulc(a[s * 8 + ta], four_step_root(fa, fb, fshift, (uint32_t)row * t1));
-                    Y[(size_t)row * kN1 + t1] = cx<T>{vv.re, T(0)};
-                }
+            row_inverse<T>(A, a, S, wv, l, tw, stw);
+            row_store<T>(Y + (size_t)row * kN1, a, row, true, wv, l, fa64, fb64, fshift);
         }
+    }
+}
+
+template <typename T, int N2, int NCB1>
+__global__ void __launch_bounds__(512)
+k2_pass2(JobTable jt, cx<T>* __restrict__ ws, const uint32_t* __restrict__ part, TileMeta* __restrict__ meta,
+         const cx<T>* __restrict__ tw, const cx<T>* __restrict__ stw, const cx<double>* __restrict__ fa64,
+         const cx<double>* __restrict__ fb64, int fshift) {
+    __shared__ __align__(16) RowSmem<T> S;
+    __shared__ uint32_t wsum;
+    const uint32_t units = jt.ntiles * (uint32_t)(N2 / 2);
+    row_smem_load<T>(S, tw, stw, threadIdx.x);
+    if constexpr (kRowPersistent<T>) {
+        for (uint32_t u = blockIdx.x; u < units; u += gridDim.x)
+            row_unit<T, N2, NCB1>(u, jt, ws, part, meta, S, wsum, tw, stw, fa64, fb64, fshift);
+    } else {
+        if (blockIdx.x < units)
+            row_unit<T, N2, NCB1>(blockIdx.x, jt, ws, part, meta, S, wsum, tw, stw, fa64, fb64, fshift);
     }
 }
 
@@ -361,9 +506,16 @@ k2_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta,
     constexpr int C = Gm::C, G = Gm::G, M = Gm::M, NJ = M / 16, CW = Gm::CW;
     constexpr uint32_t L = (uint32_t)kN1 * N2;
     constexpr int NCB = kN1 / C;
-    constexpr int SLOTS = (Gm::WAVES * kWaveSlots > M * C) ? Gm::WAVES * kWaveSlots : M * C;
-    __shared__ __align__(16) cx<T> lds[SLOTS];
-    __shared__ uint32_t obits[N2 * CW];
+    constexpr bool LT = Gm::LDS_TAB;
+    constexpr int NHT = LT ? M : 1;
+    constexpr int NBITS = N2 * CW;
+    __shared__ __align__(16) cx<T> lds[Gm::SLOTS];
+    __shared__ __align__(16) cx<T> st[LT ? wfft_lds_entries(M) : 1];
+    // Hermitian twiddles w_n2^k (k < n2/2) until the transform, then the output bits
+    __shared__ __align__(16) union {
+        cx<T> htw[NHT];
+        uint32_t obits[NBITS];
+    } U;
     __shared__ T hrow[C];
     __shared__ uint32_t s_res, s_abs, s_bad;
 
@@ -375,7 +527,9 @@ k2_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta,
     const cx<T>* __restrict__ V = ws + (size_t)lt * L;
     const int tid = threadIdx.x;
     if (tid == 0) { s_res = 0; s_abs = 0; s_bad = 0; }
-    for (int i = tid; i < N2 * CW; i += Gm::THREADS) obits[i] = 0;
+    if constexpr (!LT) {
+        for (int i = tid; i < NBITS; i += Gm::THREADS) U.obits[i] = 0;
+    }
     static_assert((M * C) % Gm::THREADS == 0, "load tile");
     constexpr int LPT = M * C / Gm::THREADS;
     {
@@ -386,6 +540,10 @@ k2_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta,
             in[q] = V[(size_t)(idx / C) * kN1 + cb * C + (idx % C)];
         }
         if (tid < C) hrow[tid] = V[(size_t)M * kN1 + cb * C + tid].re;   // H[n2/2], real
+        if constexpr (LT) {
+            wfft_load_lds<T, M>(st, stw, tid, Gm::THREADS);
+            for (int k = tid; k < M; k += Gm::THREADS) U.htw[k] = tw[k * (kN1 / N2)];
+        }
 #pragma unroll
         for (int q = 0; q < LPT; ++q) {
             const int idx = tid + q * Gm::THREADS;
@@ -411,13 +569,19 @@ k2_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta,
         } else {
             const cx<T> hm = conj(lds[tslot<C>(M - k, f)]);
             const cx<T> e = h + hm;
-            const cx<T> o = cmulc(h - hm, tw[k * (kN1 / N2)]);
+            const cx<T> wk = LT ? U.htw[k] : tw[k * (kN1 / N2)];
+            const cx<T> o = cmulc(h - hm, wk);
             v[i] = cx<T>{e.re - o.im, e.im + o.re};
         }
     }
-    __syncthreads();  // tile consumed; LDS becomes wave regions
+    __syncthreads();  // tile (and twiddles) consumed; LDS becomes wave regions (and the bit array)
+    if constexpr (LT) {
+        for (int i = tid; i < NBITS; i += Gm::THREADS) U.obits[i] = 0;
+    }
     cx<T>* reg = lds + wv * kWaveSlots + gg * (M + M / 16);
-    wave_fft<T, +1, M>(v, reg, j, stw);
+    if constexpr (LT) wave_fft_lds<T, +1, M>(v, reg, j, st);
+    else wave_fft<T, +1, M>(v, reg, j, stw);
+    if constexpr (LT) __syncthreads();   // bit array cleared
 
     float mres = 0.f, mabs = 0.f;
     uint32_t bad = 0;
@@ -436,7 +600,7 @@ k2_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta,
             bad += (uint32_t)(s2 & 1);
             mres = fmaxf(mres, (float)fabs(zz - r));
             mabs = fmaxf(mabs, (float)fabs(zz));
-            if ((s2 >> 1) & 1) atomicOr(&obits[t2 * CW + (f >> 5)], 1u << (f & 31));
+            if ((s2 >> 1) & 1) atomicOr(&U.obits[t2 * CW + (f >> 5)], 1u << (f & 31));
         }
     }
     atomicMax(&s_res, __float_as_uint(mres));
@@ -448,12 +612,12 @@ k2_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta,
         for (uint32_t idx = tid; idx < rows * CW; idx += Gm::THREADS) {
             const uint32_t t2 = idx / CW, c = idx % CW;
             const uint64_t off = (uint64_t)cb * C + 32u * c + (uint64_t)kN1 * t2;
-            if (off < limit) reinterpret_cast<uint32_t*>(g.dst)[off >> 5] = obits[t2 * CW + c];
+            if (off < limit) reinterpret_cast<uint32_t*>(g.dst)[off >> 5] = U.obits[t2 * CW + c];
         }
     } else {
         for (uint32_t t2 = tid; t2 < rows; t2 += Gm::THREADS) {
             const uint64_t off = (uint64_t)cb * C + (uint64_t)kN1 * t2;
-            if (off < limit) store_bits<C>(g.dst, off, &obits[t2 * CW]);
+            if (off < limit) store_bits<C>(g.dst, off, &U.obits[t2 * CW]);
         }
     }
     if (tid == 0) {
@@ -463,6 +627,9 @@ k2_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta,
     }
 }
 
+// Workgroups of the persistent row pass: one per compute unit (LDS-bound).
+int row_pass_workgroups();
+
 template <typename T, int N2>
 struct ClassImpl2 {
     using G1 = P1Geom<T, N2>;
@@ -471,15 +638,17 @@ struct ClassImpl2 {
     static int pass1(const JobTable& jt, void* ws, uint32_t* part, TileMeta*, const Tables& tb, void* stream) {
         dim3 grid(jt.ntiles * (kN1 / C1)), block(G1::THREADS);
         hipLaunchKernelGGL((k2_pass1<T, N2>), grid, block, 0, (hipStream_t)stream, jt, (cx<T>*)ws, part,
-                           (const cx<T>*)tb.tw, (const cx<T>*)tb.fa, (const cx<T>*)tb.fb, tb.fshift,
-                           (const cx<T>*)tb.stw);
+                           (const cx<T>*)tb.tw, (const cx<T>*)tb.stw, (const cx<double>*)tb.fa64,
+                           (const cx<double>*)tb.fb64, tb.fshift);
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
     static int pass2(const JobTable& jt, void* ws, uint32_t* part, TileMeta* meta, const Tables& tb, void* stream) {
-        dim3 grid(jt.ntiles * (N2 / 2)), block(512);
+        const uint32_t units = jt.ntiles * (N2 / 2);
+        const uint32_t wgs = kRowPersistent<T> ? (uint32_t)row_pass_workgroups() : units;
+        dim3 grid(units < wgs ? units : wgs), block(512);
         hipLaunchKernelGGL((k2_pass2<T, N2, kN1 / C1>), grid, block, 0, (hipStream_t)stream, jt, (cx<T>*)ws,
-                           (const uint32_t*)part, meta, (const cx<T>*)tb.tw, (const cx<T>*)tb.fa,
-                           (const cx<T>*)tb.fb, tb.fshift, (const cx<T>*)tb.stw);
+                           (const uint32_t*)part, meta, (const cx<T>*)tb.tw, (const cx<T>*)tb.stw,
+                           (const cx<double>*)tb.fa64, (const cx<double>*)tb.fb64, tb.fshift);
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
     static int pass3(const JobTable& jt, void* ws, uint32_t*, TileMeta* meta, const Tables& tb, void* stream) {

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "pa.h"
@@ -95,20 +96,29 @@ pa_status Ctx::tables(int prec, int logL, Tables* out) {
         ClassGeom g;
         if (!class_geometry(prec, logL, &g)) return PA_EINVAL;
         DevTables dt;
-        size_t elt = prec == PREC_FP64 ? sizeof(double) : sizeof(float);
+        // sections: tw, fa, fb, stw (element type of the class), then fa64,
+        // fb64 (FP64); each starts on a 256-byte boundary
         std::vector<unsigned char> host;
-        size_t ntw, nfa, nfb, nst;
+        size_t off[6] = {0, 0, 0, 0, 0, 0};
         auto pack = [&](auto& th) {
-            ntw = th.tw.size(); nfa = th.fa.size(); nfb = th.fb.size(); nst = th.stw.size();
-            host.resize((ntw + nfa + nfb + nst) * elt);
-            memcpy(host.data(), th.tw.data(), ntw * elt);
-            memcpy(host.data() + ntw * elt, th.fa.data(), nfa * elt);
-            memcpy(host.data() + (ntw + nfa) * elt, th.fb.data(), nfb * elt);
-            memcpy(host.data() + (ntw + nfa + nfb) * elt, th.stw.data(), nst * elt);
+            using E = typename std::remove_reference<decltype(th.tw)>::type::value_type;
+            const void* src[6] = {th.tw.data(), th.fa.data(), th.fb.data(), th.stw.data(), th.fa64.data(),
+                                  th.fb64.data()};
+            const size_t bytes[6] = {th.tw.size() * sizeof(E), th.fa.size() * sizeof(E), th.fb.size() * sizeof(E),
+                                     th.stw.size() * sizeof(E), th.fa64.size() * sizeof(double),
+                                     th.fb64.size() * sizeof(double)};
+            size_t total = 0;
+            for (int k = 0; k < 6; ++k) {
+                off[k] = total;
+                total += (bytes[k] + 255) & ~(size_t)255;
+            }
+            host.assign(total, 0);
+            for (int k = 0; k < 6; ++k)
+                if (bytes[k]) memcpy(host.data() + off[k], src[k], bytes[k]);
             dt.t.fshift = th.fshift;
         };
+        bool own64 = false;
         if (prec == PREC_NTT) {
-            elt = sizeof(uint32_t);
             TableHost<uint32_t> th;
             build_ntt_tables(logL, g.n1, g.n2, &th);
             pack(th);
@@ -116,6 +126,7 @@ pa_status Ctx::tables(int prec, int logL, Tables* out) {
             TableHost<float> th;
             build_tables<float>(logL, g.n1, g.n2, &th);
             pack(th);
+            own64 = true;
         } else {
             TableHost<double> th;
             build_tables<double>(logL, g.n1, g.n2, &th);
@@ -126,10 +137,12 @@ pa_status Ctx::tables(int prec, int logL, Tables* out) {
         if (hipMemcpy(dt.buf.ptr, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess)
             return PA_EDEVICE;
         unsigned char* base = (unsigned char*)dt.buf.ptr;
-        dt.t.tw = base;
-        dt.t.fa = base + ntw * elt;
-        dt.t.fb = base + (ntw + nfa) * elt;
-        dt.t.stw = base + (ntw + nfa + nfb) * elt;
+        dt.t.tw = base + off[0];
+        dt.t.fa = base + off[1];
+        dt.t.fb = base + off[2];
+        dt.t.stw = base + off[3];
+        dt.t.fa64 = (const double*)(own64 ? base + off[4] : base + off[1]);
+        dt.t.fb64 = (const double*)(own64 ? base + off[5] : base + off[2]);
         it = tabs.emplace(key, dt).first;
     }
     *out = it->second.t;
@@ -546,16 +559,20 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
     std::lock_guard<std::mutex> lk(c->mu);
     if (hipSetDevice(c->device) != hipSuccess) return PA_EDEVICE;
     Lane& ln = c->main;
-    int logL = 0;
-    std::vector<TilePlan> plans;
-    if (!plan_batch(ns, ms, policy, c->cost, &logL, &plans)) return PA_EINVAL;
+    std::vector<BatchGroup> groups;
+    if (!plan_batch_groups(ns, ms, policy, c->cost, &groups)) return PA_EINVAL;
+    std::vector<const TilePlan*> plan_of(count, nullptr);
     pa_stats st{};
-    for (const TilePlan& p : plans) fill_plan_stats(&st, p);
+    for (const BatchGroup& g : groups)   // ascending classes: the stats name the largest
+        for (size_t q = 0; q < g.jobs.size(); ++q) {
+            plan_of[g.jobs[q]] = &g.plans[q];
+            fill_plan_stats(&st, g.plans[q]);
+        }
     st.chunk_bits = 0;   // differ per job
     st.window_bits = 0;
 
     const bool dev = flags & PA_DEVICE_PTRS;
-    std::vector<JobDesc> jobs(count);
+    std::vector<JobDesc> all(count);
     std::vector<uint64_t> out_off(count, 0);
     if (!dev) {
         uint64_t total_words = 0;
@@ -581,11 +598,27 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
             out_off[i] = off + sw + kw;
             off += sw + kw + ow;
         }
-        fill_job(&jobs[i], dseed, dkey, dout, j.n, j.m, plans[i]);
+        fill_job(&all[i], dseed, dkey, dout, j.n, j.m, *plan_of[i]);
     }
+    // one pipeline launch per length class, in turn on the context's stream
     std::vector<pa_status> status(count, PA_OK);
-    pa_status s = ln.launch(c, plans[0].prec, logL, jobs, flags & PA_TIMING, true, &st);
-    if (s == PA_OK) s = ln.finish(c, flags, &st, &status);
+    pa_status s = PA_OK;
+    for (const BatchGroup& g : groups) {
+        std::vector<JobDesc> jobs(g.jobs.size());
+        for (size_t q = 0; q < g.jobs.size(); ++q) jobs[q] = all[g.jobs[q]];
+        std::vector<pa_status> gst(g.jobs.size(), PA_OK);
+        pa_status gs = ln.launch(c, g.plans[0].prec, g.logL, jobs, flags & PA_TIMING, true, &st);
+        if (gs == PA_OK) gs = ln.finish(c, flags, &st, &gst);
+        const bool per_tile = gs == PA_OK || gs == PA_EPRECISION;
+        for (size_t q = 0; q < g.jobs.size(); ++q) status[g.jobs[q]] = per_tile ? gst[q] : gs;
+        if (gs == PA_OK) continue;
+        if (s == PA_OK || !per_tile) s = gs;
+        if (!per_tile) break;   // device or allocation error: later groups do not run
+    }
+    if (s != PA_OK && s != PA_EPRECISION) {
+        for (uint64_t i = 0; i < count; ++i)
+            if (status[i] == PA_OK) status[i] = s;
+    }
     if (!dev && (s == PA_OK || s == PA_EPRECISION)) {
         for (uint64_t i = 0; i < count; ++i)
             if (hipMemcpyAsync(jobs_in[i].out, (uint64_t*)ln.io.ptr + out_off[i], words_of(ms[i]) * 8,

@@ -2,8 +2,11 @@
 // mod-2 sum of the intermediate keys of all blocks and batches).  Job j with
 // nchunks > 1 has nchunks stage rows of out_words words; out[w] = XOR over the
 // rows.  The rows already hold zeros beyond m, so no masking is needed.
+#include <atomic>
+
 #include "pa_internal.hpp"
 #include "conv_kernels.hpp"
+#include "conv_v2.hpp"
 
 namespace pa {
 
@@ -17,6 +20,18 @@ __global__ void __launch_bounds__(256) k_merge(JobTable jt) {
         for (uint32_t b = 0; b < jd.nchunks; ++b) acc ^= jd.stage[(uint64_t)b * words + w];
         jd.out[w] = acc;
     }
+}
+
+int row_pass_workgroups() {
+    static std::atomic<int> cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int v = cached[dev].load(std::memory_order_relaxed);
+    if (v > 0) return v;
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+    cached[dev].store(cu, std::memory_order_relaxed);
+    return cu;
 }
 
 int launch_merge(const JobTable& jt, uint64_t max_words, void* stream) {

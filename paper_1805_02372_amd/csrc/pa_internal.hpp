@@ -59,6 +59,8 @@ struct Tables {
     const void* fb;       // w_L^l, l < 1 << fshift
     int fshift;
     const void* stw;      // wave-transform stage tables, sizes 16..1024
+    const double* fa64;   // fa, fb in FP64 (for FP64 classes the same arrays as fa, fb)
+    const double* fb64;
 };
 
 typedef int (*launch_fn)(const JobTable& jt, void* ws, uint32_t* part, TileMeta* meta,

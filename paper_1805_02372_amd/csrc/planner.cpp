@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <map>
 
 namespace pa {
 
@@ -181,6 +182,63 @@ bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan*
     }
     if (found) *out = best;
     return found;
+}
+
+bool plan_batch_groups(const std::vector<uint64_t>& ns, const std::vector<uint64_t>& ms, int policy,
+                       const CostModel& cm, std::vector<BatchGroup>* groups) {
+    if (ns.empty() || ns.size() != ms.size()) return false;
+    std::map<int, BatchGroup> by_class;
+    for (size_t i = 0; i < ns.size(); ++i) {
+        TilePlan p;
+        if (!plan_job(ns[i], ms[i], policy, cm, &p)) return false;
+        BatchGroup& g = by_class[p.logL];
+        g.logL = p.logL;
+        g.jobs.push_back(i);
+        g.plans.push_back(p);
+        g.cost += p.cost - cm.launch_s;
+    }
+    std::vector<BatchGroup> gs;
+    for (auto& kv : by_class) {
+        kv.second.cost += cm.launch_s;
+        gs.push_back(std::move(kv.second));
+    }
+    // fold groups while that saves more than it costs
+    for (;;) {
+        double best_gain = 0;
+        size_t bg = 0, bh = 0;
+        std::vector<TilePlan> best_plans;
+        for (size_t g = 0; g < gs.size(); ++g)
+            for (size_t h = 0; h < gs.size(); ++h) {
+                if (g == h) continue;
+                std::vector<TilePlan> moved(gs[g].jobs.size());
+                double c = 0;
+                bool ok = true;
+                for (size_t q = 0; q < gs[g].jobs.size() && ok; ++q) {
+                    const size_t i = gs[g].jobs[q];
+                    ok = plan_at_class(ns[i], ms[i], policy, gs[h].logL, cm, &moved[q]);
+                    c += moved[q].cost - cm.launch_s;
+                }
+                if (!ok) continue;
+                const double gain = gs[g].cost - c;   // the launch of g disappears
+                if (gain > best_gain) {
+                    best_gain = gain;
+                    bg = g;
+                    bh = h;
+                    best_plans = std::move(moved);
+                }
+            }
+        if (best_gain <= 0) break;
+        BatchGroup& h = gs[bh];
+        for (size_t q = 0; q < gs[bg].jobs.size(); ++q) {
+            h.jobs.push_back(gs[bg].jobs[q]);
+            h.plans.push_back(best_plans[q]);
+            h.cost += best_plans[q].cost - cm.launch_s;
+        }
+        gs.erase(gs.begin() + (long)bg);
+    }
+    std::sort(gs.begin(), gs.end(), [](const BatchGroup& a, const BatchGroup& b) { return a.logL < b.logL; });
+    *groups = std::move(gs);
+    return true;
 }
 
 bool plan_batch(const std::vector<uint64_t>& ns, const std::vector<uint64_t>& ms, int policy,

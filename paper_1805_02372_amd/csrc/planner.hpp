@@ -1,6 +1,7 @@
 // Tile planning: FFT length class, key-chunk and output-window sizes, and the
 // rounding-error model that bounds them.  Pure host code.
 #pragma once
+#include <cstddef>
 #include <cstdint>
 #include <vector>
 
@@ -55,6 +56,21 @@ bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& 
 // limited), PREC_FP64 (smallest single tile if one fits, else the largest
 // class), PREC_NTT.
 bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan* out);
+
+// Jobs of a batch that share one FFT length class (one pipeline launch).
+struct BatchGroup {
+    int logL = 0;
+    std::vector<size_t> jobs;      // indices into the batch
+    std::vector<TilePlan> plans;   // plan of each job in `jobs`, at logL
+    double cost = 0;               // launch plus tiles
+};
+
+// Batch plan with one launch per length class: every job starts in its own
+// cheapest class, then a group is folded into another group's class while that
+// lowers the summed cost (tiles plus one launch per group).  Groups come out
+// in increasing logL.
+bool plan_batch_groups(const std::vector<uint64_t>& ns, const std::vector<uint64_t>& ms, int policy,
+                       const CostModel& cm, std::vector<BatchGroup>* groups);
 
 // One class for a whole batch: minimises the summed cost of every job's tiles.
 bool plan_batch(const std::vector<uint64_t>& ns, const std::vector<uint64_t>& ms, int policy,

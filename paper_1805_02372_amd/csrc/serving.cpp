@@ -54,13 +54,17 @@ void Ctx::serving_release() {
 
 // Tile-workspace bytes of a request at its own best FP32 plan (all tiles
 // resident at once; a launch runs fewer at a time if the budget is short).
-static uint64_t request_bytes(const CostModel& cm, uint64_t n, uint64_t m, uint64_t* min_bytes) {
+// Workspace bytes of a request's cheapest FP32 plan (all tiles resident) and
+// of one of its tiles; the plan's length class goes to *cls.
+static uint64_t request_bytes(const CostModel& cm, uint64_t n, uint64_t m, uint64_t* min_bytes, int* cls) {
     TilePlan p;
     if (!plan_job(n, m, PREC_FP32, cm, &p)) {
         *min_bytes = ~0ull;
+        *cls = 0;
         return ~0ull;
     }
     *min_bytes = (uint64_t)8 << p.logL;
+    *cls = p.logL;
     return p.tiles() * *min_bytes;
 }
 
@@ -98,14 +102,24 @@ void Ctx::serve_loop() {
         // admissions
         for (size_t i = 0; i < lanes.size() && !pending.empty() && !stop; ++i) {
             if (busy[i]) continue;
+            // continuous batching: the oldest request and the waiting requests
+            // of its length class (within a scan window), up to the lane's budget
             std::vector<Request*> batch;
             uint64_t bytes = 0;
-            while (!pending.empty() && batch.size() < 4096) {
+            int cls0 = 0;
+            std::deque<Request*> rest;
+            size_t scanned = 0;
+            while (!pending.empty()) {
                 Request* r = pending.front();
-                uint64_t bmin = 0;
-                const uint64_t b = request_bytes(cost, r->n, r->m, &bmin);
-                if (!batch.empty() && bytes + b > lane_budget) break;
                 pending.pop_front();
+                if (batch.size() >= 4096 || scanned >= 1024) {
+                    rest.push_back(r);
+                    continue;
+                }
+                ++scanned;
+                uint64_t bmin = 0;
+                int cls = 0;
+                const uint64_t b = request_bytes(cost, r->n, r->m, &bmin, &cls);
                 if (bmin > budget) {
                     r->status = PA_ENOMEM;
                     r->t_done = now_seconds();
@@ -113,10 +127,16 @@ void Ctx::serve_loop() {
                     done_cv.notify_all();
                     continue;
                 }
+                if (batch.empty()) cls0 = cls;
+                if (cls != cls0 || (!batch.empty() && bytes + b > lane_budget)) {
+                    rest.push_back(r);
+                    continue;
+                }
                 r->state = 1;
                 bytes += b;
                 batch.push_back(r);
             }
+            pending.swap(rest);
             if (batch.empty()) continue;
             std::vector<uint64_t> ns, ms;
             for (Request* r : batch) {
@@ -124,9 +144,11 @@ void Ctx::serve_loop() {
                 ms.push_back(r->m);
             }
             lk.unlock();
-            int logL = 0;
-            std::vector<TilePlan> plans;
-            pa_status s = plan_batch(ns, ms, PREC_FP32, cost, &logL, &plans) ? PA_OK : PA_EINVAL;
+            const int logL = cls0;
+            std::vector<TilePlan> plans(batch.size());
+            pa_status s = PA_OK;
+            for (size_t k = 0; k < batch.size() && s == PA_OK; ++k)
+                if (!plan_at_class(ns[k], ms[k], PREC_FP32, logL, cost, &plans[k])) s = PA_EINVAL;
             std::vector<JobDesc> jobs(batch.size());
             if (s == PA_OK) {
                 for (size_t k = 0; k < batch.size(); ++k)

@@ -48,6 +48,10 @@ void build_tables(int logL, int n1, int n2, TableHost<T>* th) {
     roots(th->tw, NT, NT, 1);
     roots(th->fa, L >> th->fshift, L, 1ull << th->fshift);
     roots(th->fb, 1ull << th->fshift, L, 1);
+    if (sizeof(T) < sizeof(double)) {
+        roots(th->fa64, L >> th->fshift, L, 1ull << th->fshift);
+        roots(th->fb64, 1ull << th->fshift, L, 1);
+    }
     // stage tables: size M, stage span Ns (> 1), radix 16: entry [k][r] = w_{16 Ns}^{k r}
     th->stw.assign(2 * (size_t)wfft_tables_total(), T(0));
     for (int lg = kWfftMinLog; lg <= kWfftMaxLog; ++lg) {

@@ -13,8 +13,11 @@ void unit_root(uint64_t e, uint64_t N, long double* c, long double* s);
 //   fa[h] = w_L^{h << fshift}, fb[l] = w_L^l, so w_L^e = fa[e >> fshift] fb[e & mask].
 //   stw: stage tables of the wave transforms of every size 16..1024 (layout
 //        in wave_fft.hpp).
+//   fa64, fb64: fa and fb in FP64 (FP32 classes only; an FP64 class uses fa
+//        and fb), for twiddles formed as FP64 products and rounded once.
 template <typename T> struct TableHost {
     std::vector<T> tw, fa, fb, stw;
+    std::vector<double> fa64, fb64;
     int fshift = 0;
 };
 

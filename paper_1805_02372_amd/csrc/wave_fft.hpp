@@ -68,9 +68,30 @@ constexpr int wfft_tables_total() { return wfft_size_offset(1 << (kWfftMaxLog + 
 constexpr int kWaveSlots = 1024 + 64;
 __device__ __forceinline__ int wslot(int e) { return e + (e >> 4); }
 
-template <typename T, int DIR, int M, int Rs, int Ns>
-__device__ __forceinline__ void wfft_stage(cx<T> (&v)[16], cx<T>* __restrict__ reg, int j,
-                                           const cx<T>* __restrict__ stw) {
+// Stage tables of one transform size M held in LDS, transposed (r-major):
+// entry (k, r) of stage Ns at wfft_stage_offset(M, Ns) + r * Ns + k, so the
+// lanes of a stage read consecutive entries (no bank conflicts).
+constexpr int wfft_lds_entries(int M) { return wfft_table_size(M) > 0 ? wfft_table_size(M) : 1; }
+
+template <typename T, int M>
+__device__ __forceinline__ void wfft_load_lds(cx<T>* __restrict__ st, const cx<T>* __restrict__ stw, int tid,
+                                              int nthreads) {
+    const cx<T>* __restrict__ base = stw + wfft_size_offset(M);
+    for (int e = tid; e < wfft_table_size(M); e += nthreads) {
+        int ns = wfft_first_radix(M), off = 0;
+        while (e >= off + ns * 16) {
+            off += ns * 16;
+            ns *= 16;
+        }
+        const int x = e - off, r = x / ns, k = x % ns;
+        st[e] = base[off + k * 16 + r];
+    }
+}
+
+// One Stockham stage.  LT: twiddles from the LDS copy `tab` (layout above),
+// else from the global tables `tab` (lane-major).
+template <typename T, int DIR, int M, int Rs, int Ns, bool LT>
+__device__ __forceinline__ void wfft_stage(cx<T> (&v)[16], cx<T>* __restrict__ reg, int j, const cx<T>* tab) {
     constexpr int R = 16, P = R / Rs, NR = M / R;
     constexpr bool LAST = (Ns * Rs == M);
 #pragma unroll
@@ -81,9 +102,15 @@ __device__ __forceinline__ void wfft_stage(cx<T> (&v)[16], cx<T>* __restrict__ r
 #pragma unroll
         for (int r = 0; r < Rs; ++r) u[r] = v[p + r * P];
         if constexpr (Ns > 1) {
-            const cx<T>* __restrict__ tk = opaque(stw) + wfft_size_offset(M) + wfft_stage_offset(M, Ns) + k * 16;
+            constexpr int OFF = wfft_stage_offset(M, Ns);
+            if constexpr (LT) {
 #pragma unroll
-            for (int r = 1; r < Rs; ++r) u[r] = twmul<DIR>(u[r], tk[r]);
+                for (int r = 1; r < Rs; ++r) u[r] = twmul<DIR>(u[r], tab[OFF + r * Ns + k]);
+            } else {
+                const cx<T>* __restrict__ tk = opaque(tab) + wfft_size_offset(M) + OFF + k * 16;
+#pragma unroll
+                for (int r = 1; r < Rs; ++r) u[r] = twmul<DIR>(u[r], tk[r]);
+            }
         }
         dft<Rs, DIR>(u);
 #pragma unroll
@@ -106,22 +133,28 @@ __device__ __forceinline__ void wfft_stage(cx<T> (&v)[16], cx<T>* __restrict__ r
     }
 }
 
-template <typename T, int DIR, int M, int Ns>
-__device__ __forceinline__ void wfft_stages(cx<T> (&v)[16], cx<T>* __restrict__ reg, int j,
-                                            const cx<T>* __restrict__ stw) {
+template <typename T, int DIR, int M, int Ns, bool LT>
+__device__ __forceinline__ void wfft_stages(cx<T> (&v)[16], cx<T>* __restrict__ reg, int j, const cx<T>* tab) {
     constexpr int Rs = (Ns == 1) ? wfft_first_radix(M) : 16;
-    wfft_stage<T, DIR, M, Rs, Ns>(v, reg, j, stw);
-    if constexpr (Ns * Rs < M) wfft_stages<T, DIR, M, Ns * Rs>(v, reg, j, stw);
+    wfft_stage<T, DIR, M, Rs, Ns, LT>(v, reg, j, tab);
+    if constexpr (Ns * Rs < M) wfft_stages<T, DIR, M, Ns * Rs, LT>(v, reg, j, tab);
 }
 
 // M-point transform of the values held by the M/16 lanes of one transform
 // group; `reg` is that group's private LDS region (>= M + M/16 slots), `j` the
-// lane within the group, `stw` the base of the stage tables of all sizes.
+// lane within the group, `stw` the base of the global stage tables of all sizes.
 template <typename T, int DIR, int M>
 __device__ __forceinline__ void wave_fft(cx<T> (&v)[16], cx<T>* __restrict__ reg, int j,
                                          const cx<T>* __restrict__ stw) {
     static_assert(M >= 16 && M <= 1024 && (M & (M - 1)) == 0, "wave transform size");
-    wfft_stages<T, DIR, M, 1>(v, reg, j, stw);
+    wfft_stages<T, DIR, M, 1, false>(v, reg, j, stw);
+}
+
+// The same with the size-M stage tables in LDS (wfft_load_lds).
+template <typename T, int DIR, int M>
+__device__ __forceinline__ void wave_fft_lds(cx<T> (&v)[16], cx<T>* __restrict__ reg, int j, const cx<T>* st) {
+    static_assert(M >= 16 && M <= 1024 && (M & (M - 1)) == 0, "wave transform size");
+    wfft_stages<T, DIR, M, 1, true>(v, reg, j, st);
 }
 
 }  // namespace pa
