@@ -44,12 +44,14 @@ template <typename T, int N2> struct P3Geom {
     // LDS with the stage tables and Hermitian twiddles copied in (the twiddles
     // share space with the output bit array) vs without; copy them only when
     // the workgroups per CU (160 KB of LDS) stay the same.
-    static constexpr size_t kBits = (size_t)N2 * CW * 4;
+    static constexpr size_t kBits = (size_t)WAVES * 64 * 4;   // 32 output bits per lane
     static constexpr size_t kHtw = (size_t)M * sizeof(cx<T>);
     static constexpr size_t kBase = (size_t)SLOTS * sizeof(cx<T>) + C * sizeof(T) + 64;
     static constexpr size_t kWithout = kBase + kBits;
     static constexpr size_t kWith = kBase + (kBits > kHtw ? kBits : kHtw) + wfft_lds_entries(M) * sizeof(cx<T>);
     static constexpr bool LDS_TAB = kWith <= 163840 && (163840 / kWith) >= (163840 / kWithout);
+    // workgroups per CU that the LDS allows; registers are capped to match
+    static constexpr int MIN_WG = (163840 / (LDS_TAB ? kWith : kWithout)) >= 2 ? 2 : 1;
 };
 
 // Transposition tile: row k2 of C elements, columns XOR-swizzled by the row.
@@ -192,10 +194,15 @@ k2_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const
         const int i = j + q * LPG;
         cf[q] = root64(fa64, fb64, fshift, i < 16 ? CSTEP * t1 * (uint32_t)i : 0u);
     }
+    // bit f of row r from the 32-bit half holding it (unconditional reads, selects)
+    const uint32_t* __restrict__ kb32 = reinterpret_cast<const uint32_t*>(kbits) + (f >> 5);
+    const uint32_t* __restrict__ sb32 = reinterpret_cast<const uint32_t*>(sbits) + (f >> 5);
+    const uint32_t fs = (uint32_t)f & 31u;
     auto z = [&](int r) -> cx<T> {
-        const T xb = (T)((kbits[r] >> f) & 1u);
-        T wb = T(0);
-        if (t1 + (uint32_t)kN1 * (uint32_t)r < win) wb = ((sbits[r] >> f) & 1u) ? T(1) : T(-1);
+        const uint32_t kw = kb32[2 * r], sw = sb32[2 * r];
+        const T xb = ((kw >> fs) & 1u) ? T(1) : T(0);
+        const T sv = ((sw >> fs) & 1u) ? T(1) : T(-1);
+        const T wb = (t1 + (uint32_t)kN1 * (uint32_t)r < win) ? sv : T(0);
         return cx<T>{xb, wb};
     };
     cx<T> v[16];
@@ -490,16 +497,16 @@ k2_pass2(JobTable jt, cx<T>* __restrict__ ws, const uint32_t* __restrict__ part,
 }
 
 // ------------------------------------------------------------------ pass 3
-template <int C> __device__ __forceinline__ void store_bits(uint64_t* dst, uint64_t off, const uint32_t* w);
-template <> __device__ __forceinline__ void store_bits<8>(uint64_t* dst, uint64_t off, const uint32_t* w) {
-    reinterpret_cast<uint8_t*>(dst)[off >> 3] = (uint8_t)w[0];
-}
-template <> __device__ __forceinline__ void store_bits<16>(uint64_t* dst, uint64_t off, const uint32_t* w) {
-    reinterpret_cast<uint16_t*>(dst)[off >> 4] = (uint16_t)w[0];
+// rint(z) mod 4 for an integral r (FP32: |r| < 2^31; FP64: |r| < 2^51)
+__device__ __forceinline__ uint32_t low2(float r) { return (uint32_t)(int)r & 3u; }
+__device__ __forceinline__ uint32_t low2(double r) {
+    const double q = r * 0.25;
+    return (uint32_t)(int)((q - floor(q)) * 4.0) & 3u;
 }
 
 template <typename T, int N2>
 __global__ void __launch_bounds__((P3Geom<T, N2>::THREADS))
+__attribute__((amdgpu_waves_per_eu(P3Geom<T, N2>::MIN_WG * P3Geom<T, N2>::WAVES / 4)))
 k2_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta, const cx<T>* __restrict__ tw,
          const cx<T>* __restrict__ stw) {
     using Gm = P3Geom<T, N2>;
@@ -508,13 +515,15 @@ k2_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta,
     constexpr int NCB = kN1 / C;
     constexpr bool LT = Gm::LDS_TAB;
     constexpr int NHT = LT ? M : 1;
-    constexpr int NBITS = N2 * CW;
+    constexpr int NLB = Gm::WAVES * 64;
     __shared__ __align__(16) cx<T> lds[Gm::SLOTS];
     __shared__ __align__(16) cx<T> st[LT ? wfft_lds_entries(M) : 1];
-    // Hermitian twiddles w_n2^k (k < n2/2) until the transform, then the output bits
+    // Hermitian twiddles w_n2^k (k < n2/2) until the transform, then the
+    // output bits of each lane: bit 2 i + e of lbits[w * 64 + g NJ + j] is the
+    // output of column w G + g, row 2 (j + NJ i) + e
     __shared__ __align__(16) union {
         cx<T> htw[NHT];
-        uint32_t obits[NBITS];
+        uint32_t lbits[NLB];
     } U;
     __shared__ T hrow[C];
     __shared__ uint32_t s_res, s_abs, s_bad;
@@ -527,9 +536,6 @@ k2_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta,
     const cx<T>* __restrict__ V = ws + (size_t)lt * L;
     const int tid = threadIdx.x;
     if (tid == 0) { s_res = 0; s_abs = 0; s_bad = 0; }
-    if constexpr (!LT) {
-        for (int i = tid; i < NBITS; i += Gm::THREADS) U.obits[i] = 0;
-    }
     static_assert((M * C) % Gm::THREADS == 0, "load tile");
     constexpr int LPT = M * C / Gm::THREADS;
     {
@@ -574,51 +580,56 @@ k2_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta,
             v[i] = cx<T>{e.re - o.im, e.im + o.re};
         }
     }
-    __syncthreads();  // tile (and twiddles) consumed; LDS becomes wave regions (and the bit array)
-    if constexpr (LT) {
-        for (int i = tid; i < NBITS; i += Gm::THREADS) U.obits[i] = 0;
-    }
+    __syncthreads();  // tile (and twiddles) consumed; LDS becomes wave regions
     cx<T>* reg = lds + wv * kWaveSlots + gg * (M + M / 16);
     if constexpr (LT) wave_fft_lds<T, +1, M>(v, reg, j, st);
     else wave_fft<T, +1, M>(v, reg, j, stw);
-    if constexpr (LT) __syncthreads();   // bit array cleared
 
+    // window, exact rounding and parity (branch-free): only the low two bits
+    // of rint(z) + weight matter, bit = bit 1, parity check = bit 0
+    const uint32_t wlow = meta[t].popcnt & 3u;
+    const uint32_t bo = (uint32_t)g.bo;
+    const uint32_t rows = (bo + (uint32_t)kN1 - 1u) / (uint32_t)kN1;  // rows t2 holding outputs
     float mres = 0.f, mabs = 0.f;
     uint32_t bad = 0;
-    const uint32_t rows = (uint32_t)((g.bo + kN1 - 1) / kN1);  // rows t2 holding outputs
+    uint32_t mybits = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const uint32_t t2 = 2u * (uint32_t)(j + i * NJ) + (uint32_t)e;
-            if (t2 >= rows) continue;
-            const uint64_t vo = (uint64_t)t1 + (uint64_t)kN1 * t2;
-            if (vo >= g.bo) continue;
+            const bool valid = t1 + (uint32_t)kN1 * t2 < bo;
             const T zz = e ? v[i].im : v[i].re;
             const T r = round_even(zz);
-            const int64_t s2 = (int64_t)r + weight;
-            bad += (uint32_t)(s2 & 1);
-            mres = fmaxf(mres, (float)fabs(zz - r));
-            mabs = fmaxf(mabs, (float)fabs(zz));
-            if ((s2 >> 1) & 1) atomicOr(&U.obits[t2 * CW + (f >> 5)], 1u << (f & 31));
+            const uint32_t s2 = low2(r) + wlow;
+            bad += (valid && (s2 & 1u)) ? 1u : 0u;
+            mres = fmaxf(mres, valid ? (float)fabs(zz - r) : 0.f);
+            mabs = fmaxf(mabs, valid ? (float)fabs(zz) : 0.f);
+            mybits |= (valid ? ((s2 >> 1) & 1u) : 0u) << (2 * i + e);
         }
     }
+    U.lbits[wv * 64 + l] = mybits;
     atomicMax(&s_res, __float_as_uint(mres));
     atomicMax(&s_abs, __float_as_uint(mabs));
     atomicAdd(&s_bad, bad);
     __syncthreads();
+    // assemble and store each output row's C bits (32 per word, C < 32: one C-bit group)
+    constexpr int WB = C < 32 ? C : 32;    // bits per stored word
     const uint64_t limit = g.dst_words * 64u;
-    if constexpr (C >= 32) {
-        for (uint32_t idx = tid; idx < rows * CW; idx += Gm::THREADS) {
-            const uint32_t t2 = idx / CW, c = idx % CW;
-            const uint64_t off = (uint64_t)cb * C + 32u * c + (uint64_t)kN1 * t2;
-            if (off < limit) reinterpret_cast<uint32_t*>(g.dst)[off >> 5] = U.obits[t2 * CW + c];
+    for (uint32_t idx = tid; idx < rows * CW; idx += Gm::THREADS) {
+        const uint32_t t2 = idx / CW, c = idx % CW;
+        const uint32_t k = t2 >> 1, sh = 2u * (k / NJ) + (t2 & 1u), jj = k % NJ;
+        uint32_t word = 0;
+#pragma unroll
+        for (int q = 0; q < WB; ++q) {
+            const int col = 32 * (int)c + q;
+            word |= ((U.lbits[(col / G) * 64 + (col % G) * NJ + jj] >> sh) & 1u) << q;
         }
-    } else {
-        for (uint32_t t2 = tid; t2 < rows; t2 += Gm::THREADS) {
-            const uint64_t off = (uint64_t)cb * C + (uint64_t)kN1 * t2;
-            if (off < limit) store_bits<C>(g.dst, off, &U.obits[t2 * CW]);
-        }
+        const uint64_t off = (uint64_t)cb * C + 32u * c + (uint64_t)kN1 * t2;
+        if (off >= limit) continue;
+        if constexpr (C >= 32) reinterpret_cast<uint32_t*>(g.dst)[off >> 5] = word;
+        else if constexpr (C == 16) reinterpret_cast<uint16_t*>(g.dst)[off >> 4] = (uint16_t)word;
+        else reinterpret_cast<uint8_t*>(g.dst)[off >> 3] = (uint8_t)word;
     }
     if (tid == 0) {
         atomicMax(&meta[t].maxres, s_res);

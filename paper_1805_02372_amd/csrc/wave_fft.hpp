@@ -73,19 +73,20 @@ __device__ __forceinline__ int wslot(int e) { return e + (e >> 4); }
 // lanes of a stage read consecutive entries (no bank conflicts).
 constexpr int wfft_lds_entries(int M) { return wfft_table_size(M) > 0 ? wfft_table_size(M) : 1; }
 
+template <typename T, int M, int Ns>
+__device__ __forceinline__ void wfft_load_lds_from(cx<T>* __restrict__ st, const cx<T>* __restrict__ base, int tid,
+                                                   int nthreads) {
+    if constexpr (Ns < M) {
+        constexpr int OFF = wfft_stage_offset(M, Ns);
+        for (int x = tid; x < Ns * 16; x += nthreads) st[OFF + x] = base[OFF + (x % Ns) * 16 + x / Ns];
+        wfft_load_lds_from<T, M, Ns * 16>(st, base, tid, nthreads);
+    }
+}
+
 template <typename T, int M>
 __device__ __forceinline__ void wfft_load_lds(cx<T>* __restrict__ st, const cx<T>* __restrict__ stw, int tid,
                                               int nthreads) {
-    const cx<T>* __restrict__ base = stw + wfft_size_offset(M);
-    for (int e = tid; e < wfft_table_size(M); e += nthreads) {
-        int ns = wfft_first_radix(M), off = 0;
-        while (e >= off + ns * 16) {
-            off += ns * 16;
-            ns *= 16;
-        }
-        const int x = e - off, r = x / ns, k = x % ns;
-        st[e] = base[off + k * 16 + r];
-    }
+    wfft_load_lds_from<T, M, wfft_first_radix(M)>(st, stw + wfft_size_offset(M), tid, nthreads);
 }
 
 // One Stockham stage.  LT: twiddles from the LDS copy `tab` (layout above),
