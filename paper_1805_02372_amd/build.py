@@ -20,9 +20,12 @@ SOURCES = ["conv_fp32.hip", "conv_fp64.hip", "ntt.hip", "merge.hip",
            "engine.cpp", "serving.cpp", "tuner.cpp", "planner.cpp", "tables.cpp"]
 
 # Packed FP32 instructions are disabled for all device code.  Code object v5
-# loads in every ROCm 6/7 runtime, including the one PyTorch bundles.
+# loads in every ROCm 6/7 runtime, including the one PyTorch bundles.  Atomics
+# on one address from a whole wave are combined with DPP reductions (the
+# default combines them lane by lane in a scalar loop).
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-atomic-optimizer-strategy=DPP",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

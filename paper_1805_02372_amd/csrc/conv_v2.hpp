@@ -346,7 +346,7 @@ __device__ __forceinline__ void row_inverse(cx<T> (&P)[16], cx<T> (&a)[16], RowS
 #pragma unroll
         for (int i = 0; i < 16; ++i) P[i] = cmulc(P[i], w8192<T>(S, tw, wv, l + 64 * i));
     }
-    __syncthreads();
+    wave_sync();   // the wave's own region: no other wave uses it until the barrier below
 #pragma unroll
     for (int i = 0; i < 16; ++i) reg[wslot(l + 64 * i)] = P[i];
     __syncthreads();
@@ -364,7 +364,7 @@ __device__ __forceinline__ void row_inverse(cx<T> (&P)[16], cx<T> (&a)[16], RowS
 template <typename T>
 __device__ __forceinline__ void row_mirror(cx<T> (&X)[16], cx<T>* lds, int wv, int l, bool zero) {
     constexpr int S = kWaveSlots;
-    __syncthreads();
+    wave_sync();   // X was produced in the wave's own region, which no other wave touches
 #pragma unroll
     for (int i = 0; i < 16; ++i) lds[wv * S + wslot(l + 64 * i)] = X[i];
     __syncthreads();
@@ -595,6 +595,7 @@ k2_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta,
     uint32_t mybits = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
+        if (2u * (uint32_t)(i * NJ) >= rows) continue;   // register i holds no output row (uniform)
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const uint32_t t2 = 2u * (uint32_t)(j + i * NJ) + (uint32_t)e;
