@@ -151,13 +151,16 @@ const char* pa_strerror(pa_status status);
 
 /* ---- tuning ----------------------------------------------------------------- */
 
-/* Measure the cost of one tile of every FFT length class 2^12..2^24 (section
+/* Measure the cost of a tile of every FFT length class 2^12..2^24 (section
  * 3, step 2: the planner picks block and batch sizes from measured costs) for
  * the precisions selected by flags (PA_PREC_AUTO: FP32 and FP64; otherwise the
  * one named), with `reps` timed runs each on synthetic bits, and use the
- * results in this context's planner.  If path is not NULL the table is also
- * written there as JSON ({"fp32": {"12": seconds, ...}, ...}).  Synchronous;
- * PA_EDEVICE on a HIP error, PA_EINVAL for a file that cannot be written. */
+ * results in this context's planner.  Each class runs one launch with one tile
+ * and one with four: the marginal cost per tile goes to the class and the
+ * remainder (median over classes) to the per-launch cost.  If path is not NULL
+ * the table is also written there as JSON ({"launch": seconds, "fp32": {"12":
+ * seconds, ...}, ...}).  Synchronous; PA_EDEVICE on a HIP error, PA_EINVAL for
+ * a file that cannot be written. */
 pa_status pa_tune(pa_ctx* ctx, uint32_t flags, int reps, const char* path);
 
 /* Load a table written by pa_tune into this context's planner.  A context

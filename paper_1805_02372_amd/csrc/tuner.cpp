@@ -1,10 +1,12 @@
 // Tuner: measured per-tile cost of every FFT length class (paper section 3,
 // step 2 sizes blocks and batches from the resources and the precision the
 // transform needs; here the planner minimises the summed measured cost of a
-// plan's tiles).  Runs each class on one synthetic tile (key and seed bits from
-// a fixed xorshift generator) and times the kernel passes with HIP events.
+// plan's tiles plus one launch cost per launch).  Runs each class on synthetic
+// tiles (key and seed bits from a fixed xorshift generator) and times the
+// kernel passes with HIP events.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -27,9 +29,9 @@ static const char* prec_key(int prec) { return prec == PREC_FP32 ? "fp32" : prec
 static pa_status save_json(const CostModel& cm, const std::vector<int>& precs, const char* path) {
     FILE* f = fopen(path, "w");
     if (!f) return PA_EINVAL;
-    fprintf(f, "{");
+    fprintf(f, "{\"launch\": %.9g", cm.launch_s);
     for (size_t i = 0; i < precs.size(); ++i) {
-        fprintf(f, "%s\"%s\": {", i ? ", " : "", prec_key(precs[i]));
+        fprintf(f, ", \"%s\": {", prec_key(precs[i]));
         for (int k = 12; k <= 24; ++k) fprintf(f, "%s\"%d\": %.9g", k > 12 ? ", " : "", k, cm.tile(precs[i], k));
         fprintf(f, "}");
     }
@@ -47,6 +49,11 @@ static pa_status load_json(CostModel& cm, const char* path) {
     while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
     fclose(f);
     int loaded = 0;
+    const size_t la = text.find("\"launch\":");
+    if (la != std::string::npos) {
+        const double v = strtod(text.c_str() + la + 9, nullptr);
+        if (v >= 0 && v < 1.0) cm.launch_s = v;
+    }
     for (int prec : {PREC_FP32, PREC_FP64, PREC_NTT}) {
         const std::string tag = std::string("\"") + prec_key(prec) + "\"";
         size_t at = text.find(tag);
@@ -68,6 +75,29 @@ static pa_status load_json(CostModel& cm, const char* path) {
     return loaded ? PA_OK : PA_EINVAL;
 }
 
+// Kernel time (s) of one launch of `count` identical one-tile jobs of class k.
+static pa_status time_launch(Ctx* c, int prec, int k, const TilePlan& p, int count, uint64_t* dseed,
+                             uint64_t* dkey, uint64_t* douts, uint64_t out_words, int reps, double* best) {
+    const uint64_t L = 1ull << k;
+    *best = 1e30;
+    for (int r = 0; r <= reps; ++r) {  // the first run warms tables and workspace
+        std::vector<JobDesc> jobs(count);
+        for (int q = 0; q < count; ++q)
+            fill_job(&jobs[q], dseed, dkey, douts + q * out_words, L / 2, L / 2 + 1, p);
+        pa_stats ps{};
+        pa_status st = c->main.launch(c, prec, k, jobs, true, true, &ps);
+        if (st == PA_OK) st = c->main.finish(c, PA_TIMING | PA_NO_FALLBACK, &ps, nullptr);
+        if (st != PA_OK && st != PA_EPRECISION) return st;
+        const double ms = ps.ms_pass[0] + ps.ms_pass[1] + ps.ms_pass[2] + ps.ms_pass[3];
+        if (r > 0 && ms > 0) *best = std::min(*best, ms * 1e-3);
+    }
+    return PA_OK;
+}
+
+// Per class: kernel time of one launch with 1 tile (T1) and with 4 tiles (T4);
+// the marginal tile cost (T4 - T1) / 3 goes to the class, the rest (T1 minus
+// one tile: ramp-up and tail of the launch) to the per-launch cost (median
+// over the classes measured).
 pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path) {
     std::vector<int> precs;
     switch (flags & PA_PREC_MASK) {
@@ -78,45 +108,46 @@ pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path) {
         default: return PA_EINVAL;
     }
     if (reps < 1) reps = 1;
-    Lane& ln = c->main;
+    constexpr int kMany = 4;
     const uint64_t maxL = 1ull << 24;
     // synthetic job: n = L/2, m = L/2 + 1 fills one tile of class L exactly
-    const uint64_t words = (maxL + 64) / 64 + 2;
+    const uint64_t words = (maxL + 64) / 64 + 2, out_words = maxL / 2 / 64 + 2;
     std::vector<uint64_t> host(2 * words);
     uint64_t s = 0x9E3779B97F4A7C15ull;
     for (uint64_t& w : host) w = xorshift(s);
     DevBuf buf;
-    pa_status st = buf.ensure(c, (2 * words + words) * 8);
+    pa_status st = buf.ensure(c, (2 * words + kMany * out_words) * 8);
     if (st != PA_OK) return st;
     uint64_t* dseed = (uint64_t*)buf.ptr;
     uint64_t* dkey = dseed + words;
-    uint64_t* dout = dkey + words;
+    uint64_t* douts = dkey + words;
     if (hipMemcpy(dseed, host.data(), 2 * words * 8, hipMemcpyHostToDevice) != hipSuccess) {
         buf.release(c);
         return PA_EDEVICE;
     }
+    std::vector<double> fixed;
     for (int prec : precs)
         for (int k = 12; k <= 24; ++k) {
             const uint64_t L = 1ull << k;
             TilePlan p;
             if (!plan_at_class(L / 2, L / 2 + 1, prec, k, c->cost, &p) || p.tiles() != 1) continue;
-            double best = 1e30;
-            for (int r = 0; r <= reps; ++r) {  // first run warms tables and workspace
-                std::vector<JobDesc> jobs(1);
-                fill_job(&jobs[0], dseed, dkey, dout, L / 2, L / 2 + 1, p);
-                pa_stats ps{};
-                st = ln.launch(c, prec, k, jobs, true, true, &ps);
-                if (st == PA_OK) st = ln.finish(c, PA_TIMING | PA_NO_FALLBACK, &ps, nullptr);
-                if (st != PA_OK && st != PA_EPRECISION) {
-                    buf.release(c);
-                    return st;
-                }
-                const double ms = ps.ms_pass[0] + ps.ms_pass[1] + ps.ms_pass[2] + ps.ms_pass[3];
-                if (r > 0 && ms > 0) best = std::min(best, ms * 1e-3);
+            double t1 = 0, t4 = 0;
+            st = time_launch(c, prec, k, p, 1, dseed, dkey, douts, out_words, reps, &t1);
+            if (st == PA_OK) st = time_launch(c, prec, k, p, kMany, dseed, dkey, douts, out_words, reps, &t4);
+            if (st != PA_OK) {
+                buf.release(c);
+                return st;
             }
-            if (best < 1e30) c->cost.set(prec, k, best);
+            if (t1 >= 1e30 || t4 >= 1e30) continue;
+            const double marginal = std::max((t4 - t1) / (kMany - 1), 0.1 * t1);
+            c->cost.set(prec, k, marginal);
+            fixed.push_back(std::max(t1 - marginal, 0.0));
         }
     buf.release(c);
+    if (!fixed.empty()) {
+        std::sort(fixed.begin(), fixed.end());
+        c->cost.launch_s = fixed[fixed.size() / 2];
+    }
     if (path) return save_json(c->cost, precs, path);
     return PA_OK;
 }

@@ -258,6 +258,7 @@ def test_tune_writes_and_loads(pa, ctx, tmp_path):
     data = json.load(open(path))
     costs = [data["fp32"][str(k)] for k in range(12, 25)]
     assert all(c > 0 for c in costs)
+    assert 0 <= data["launch"] < 1e-2   # per-launch cost in seconds
     assert costs[-1] > costs[0]          # longer transforms cost more
     c2 = pa.pa_create(0, 0, None)
     try:
