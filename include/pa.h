@@ -91,8 +91,11 @@ typedef struct {
 /* Hash `count` independent jobs (uneven n and m).  Jobs are grouped by FFT
  * length class (each job's cheapest class, groups folded together while that
  * lowers the summed cost); each group runs as one launch per pipeline pass for
- * all its tiles.  Tile and segment sizes come from the cost model (tuned when
- * pa_tune ran).  pa_last_stats then names the largest class used.
+ * all its tiles.  The groups run concurrently on the context's stream and on
+ * PA_BATCH_LANES - 1 side streams of the context (default 3 streams in all),
+ * forked from the context's stream.  Tile and segment sizes come from the cost
+ * model (tuned when pa_tune ran).  pa_last_stats then names the largest class
+ * used.
  * per_job (optional, count entries) receives each job's status; the return
  * value is PA_OK only if every job succeeded.  Pointer kind per PA_DEVICE_PTRS
  * as for pa_hash.  Synchronous. */

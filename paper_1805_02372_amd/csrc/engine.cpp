@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <type_traits>
@@ -483,6 +484,7 @@ void pa_destroy(pa_ctx* ctx) {
     (void)hipSetDevice(c->device);
     c->serving_shutdown();
     c->main.release(c);
+    for (Lane& ln : c->side) ln.release(c);
     c->serving_release();
     for (auto& kv : c->tabs) kv.second.buf.release(c);
     delete c;
@@ -537,6 +539,30 @@ pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, con
     c->last = st;
     return s;
 }
+
+}  // extern "C"
+
+namespace pa {
+// Side streams for batches: PA_BATCH_LANES (default 3, 1..8) streams in all,
+// the context's stream included.  Called with the context mutex held.
+pa_status ensure_side_lanes(Ctx* c) {
+    const char* e = getenv("PA_BATCH_LANES");
+    const int want = std::max(1, std::min(e ? atoi(e) : 3, 8)) - 1;
+    if ((int)c->side.size() >= want) return PA_OK;
+    while ((int)c->side.size() < want) {
+        c->side.emplace_back();
+        Lane& ln = c->side.back();
+        if (hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) != hipSuccess) {
+            c->side.pop_back();
+            return PA_EDEVICE;
+        }
+        ln.own_stream = true;
+    }
+    return PA_OK;
+}
+}  // namespace pa
+
+extern "C" {
 
 pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint32_t flags, pa_status* per_job) {
     if (!ctx || (!jobs_in && count)) return PA_EINVAL;
@@ -600,20 +626,67 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
         }
         fill_job(&all[i], dseed, dkey, dout, j.n, j.m, *plan_of[i]);
     }
-    // one pipeline launch per length class, in turn on the context's stream
+    // One pipeline launch per length class.  The groups run concurrently on
+    // the context's stream and on side streams (forked from it), largest
+    // first; a stream takes the next group as soon as its launch is finished.
     std::vector<pa_status> status(count, PA_OK);
-    pa_status s = PA_OK;
-    for (const BatchGroup& g : groups) {
-        std::vector<JobDesc> jobs(g.jobs.size());
-        for (size_t q = 0; q < g.jobs.size(); ++q) jobs[q] = all[g.jobs[q]];
+    pa_status s = ensure_side_lanes(c);
+    if (s != PA_OK) return s;
+    std::vector<Lane*> lanes{&ln};
+    for (Lane& sl : c->side) lanes.push_back(&sl);
+    if (lanes.size() > 1) {
+        hipEvent_t fork = nullptr;
+        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return PA_EDEVICE;
+        bool ok = hipEventRecord(fork, ln.stream) == hipSuccess;
+        for (size_t k = 1; k < lanes.size() && ok; ++k) ok = hipStreamWaitEvent(lanes[k]->stream, fork, 0) == hipSuccess;
+        (void)hipEventDestroy(fork);
+        if (!ok) return PA_EDEVICE;
+    }
+    std::vector<size_t> order(groups.size());
+    for (size_t g = 0; g < order.size(); ++g) order[g] = g;
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return groups[a].cost > groups[b].cost; });
+    std::vector<int> on_lane(lanes.size(), -1);          // group running on each lane
+    std::vector<pa_stats> lst(lanes.size(), pa_stats{});
+    std::deque<size_t> queue(order.begin(), order.end());
+    std::deque<size_t> fifo;                              // lanes in launch order
+    bool stop = false;
+    while (true) {
+        for (size_t k = 0; k < lanes.size() && !stop && !queue.empty(); ++k) {
+            if (on_lane[k] >= 0) continue;
+            const BatchGroup& g = groups[queue.front()];
+            std::vector<JobDesc> jobs(g.jobs.size());
+            for (size_t q = 0; q < g.jobs.size(); ++q) jobs[q] = all[g.jobs[q]];
+            const pa_status ls = lanes[k]->launch(c, g.plans[0].prec, g.logL, jobs, flags & PA_TIMING, true, &lst[k]);
+            if (ls != PA_OK) {
+                for (size_t q = 0; q < g.jobs.size(); ++q) status[g.jobs[q]] = ls;
+                s = ls;
+                stop = true;   // device or allocation error: no further groups are started
+                break;
+            }
+            on_lane[k] = (int)queue.front();
+            queue.pop_front();
+            fifo.push_back(k);
+        }
+        if (fifo.empty()) break;
+        const size_t k = fifo.front();
+        fifo.pop_front();
+        const BatchGroup& g = groups[(size_t)on_lane[k]];
+        on_lane[k] = -1;
         std::vector<pa_status> gst(g.jobs.size(), PA_OK);
-        pa_status gs = ln.launch(c, g.plans[0].prec, g.logL, jobs, flags & PA_TIMING, true, &st);
-        if (gs == PA_OK) gs = ln.finish(c, flags, &st, &gst);
+        const pa_status gs = lanes[k]->finish(c, flags, &lst[k], &gst);
         const bool per_tile = gs == PA_OK || gs == PA_EPRECISION;
         for (size_t q = 0; q < g.jobs.size(); ++q) status[g.jobs[q]] = per_tile ? gst[q] : gs;
-        if (gs == PA_OK) continue;
-        if (s == PA_OK || !per_tile) s = gs;
-        if (!per_tile) break;   // device or allocation error: later groups do not run
+        if (gs != PA_OK && (s == PA_OK || !per_tile)) s = gs;
+        if (!per_tile) stop = true;
+        if (stop) queue.clear();
+    }
+    for (const pa_stats& x : lst) {
+        st.tiles += x.tiles;
+        st.fallback_tiles += x.fallback_tiles;
+        st.launches += x.launches;
+        st.max_residual = std::max(st.max_residual, x.max_residual);
+        st.max_abs = std::max(st.max_abs, x.max_abs);
+        for (int q = 0; q < 4; ++q) st.ms_pass[q] += x.ms_pass[q];
     }
     if (s != PA_OK && s != PA_EPRECISION) {
         for (uint64_t i = 0; i < count; ++i)

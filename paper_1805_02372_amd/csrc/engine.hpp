@@ -97,6 +97,7 @@ struct Ctx {
     std::mutex mu;        // serialises the public calls that use `main`
     std::mutex tab_mu;    // twiddle table cache
     Lane main;
+    std::vector<Lane> side;   // extra streams for the length-class groups of a batch
     std::map<int, DevTables> tabs;
     CostModel cost;
     pa_stats last{};

@@ -221,9 +221,13 @@ pa_status pa_submit(pa_ctx* ctx, uint32_t seed_id, uint64_t n, uint64_t m, const
             // the budget so that the serving lanes get their shares (it grows
             // again on the next direct call)
             std::lock_guard<std::mutex> g(c->mu);
-            c->main.ws.release(c);
-            c->main.part.release(c);
-            c->main.stage.release(c);
+            std::vector<Lane*> direct{&c->main};
+            for (Lane& ln : c->side) direct.push_back(&ln);
+            for (Lane* ln : direct) {
+                ln->ws.release(c);
+                ln->part.release(c);
+                ln->stage.release(c);
+            }
         }
         std::vector<Lane> lanes(serve_lanes());
         for (Lane& ln : lanes) {
