@@ -4,7 +4,7 @@
 Workload (default): one hash with n = 12,345,679 key bits and m = 1,234,567
 output bits, i.i.d. uniform bits from seed 2 (synth.single_config("c3")),
 inputs resident in HBM before timing starts.  A step is one complete pa_hash
-call (plan, every tile's three kernel passes, XOR merge, certificate
+call (plan, every tile's three kernel passes with the XOR merge, certificate
 read-back), timed over K steps between device synchronisations.
 
 Reported: the headline FP32-segmented (auto) throughput, the plain FP64
@@ -37,7 +37,7 @@ def log(*a):
 
 
 KERNEL_SOURCES = ("conv_fp32.hip", "conv_fp64.hip", "conv_kernels.hpp", "conv_v2.hpp", "fft_core.hpp",
-                  "wave_fft.hpp", "merge.hip", "ntt.hip", "pa_internal.hpp")
+                  "wave_fft.hpp", "ntt.hip", "pa_internal.hpp")
 
 
 def kernel_source_digest() -> str:
@@ -55,17 +55,19 @@ def launch_bytes(st: dict, n: int, m: int) -> list[float]:
     job (e = 8 for FP32, 16 for FP64; L the FFT length; T tiles = C chunks x
     W windows):
       pass 1: reads each tile's key chunk and seed slice, writes the complex
-              array: e L T + (2 W n + C m) / 8
+              array (and clears the output when C > 1):
+              e L T + (2 W n + C m) / 8 [+ m / 8]
       pass 2: reads the array, writes half of it: 1.5 e L T
-      pass 3: reads the half, writes each tile's output window: 0.5 e L T + C m / 8
-      merge:  reads the C partial hashes, writes the hash: (C + 1) m / 8 (C > 1)"""
+      pass 3: reads the half, writes (C = 1) or XORs in (C > 1) each tile's
+              output window: 0.5 e L T + C m / 8
+    The fourth entry (the former merge) is 0: chunks are XOR-accumulated."""
     e = 16 if st["prec"] == 0x20 else 8
     L = float(1 << st["log2_len"])
     C = -(-n // st["chunk_bits"])
     W = -(-m // st["window_bits"])
     T = C * W
-    merge = (C + 1) * m / 8 if C > 1 else 0.0
-    return [e * L * T + (2 * W * n + C * m) / 8, 1.5 * e * L * T, 0.5 * e * L * T + C * m / 8, merge]
+    clear = m / 8 if C > 1 else 0.0
+    return [e * L * T + (2 * W * n + C * m) / 8 + clear, 1.5 * e * L * T, 0.5 * e * L * T + C * m / 8, 0.0]
 
 
 def run_single(pa, ctx, torch, prob, flags, steps, warmup):

@@ -141,7 +141,8 @@ typedef struct {
     double max_residual;      /* max |z - rint z| over all outputs            */
     double max_abs;           /* max |z| over all outputs                     */
     double bound;             /* predicted max error of the plan              */
-    double ms_pass[4];        /* PA_TIMING: summed kernel ms of pass 1,2,3, merge */
+    double ms_pass[4];        /* PA_TIMING: summed kernel ms of pass 1, 2, 3; [3] is 0
+                                 (key chunks are XOR-merged inside pass 3)  */
     uint64_t model_bytes;     /* algorithmic HBM bytes of the FFT passes      */
     uint64_t launches;        /* kernel launches                              */
 } pa_stats;

@@ -43,8 +43,10 @@ __device__ __forceinline__ JobDesc find_job(const JobTable& jt, uint32_t t) {
 
 struct TileGeo {
     uint64_t j0, bi, i0, bo, sigma;
-    uint64_t* dst;        // output words of this tile (bit 0 = output i0)
+    uint64_t* dst;        // output words of this tile's window (bit 0 = output i0)
     uint64_t dst_words;
+    bool accumulate;      // several key chunks: XOR into dst (cleared by the chunk-0 tile)
+    bool clears;          // this tile is chunk 0 of an accumulated window
 };
 
 __device__ __forceinline__ TileGeo tile_geo(const JobDesc& jd, uint32_t lt) {
@@ -58,9 +60,35 @@ __device__ __forceinline__ TileGeo tile_geo(const JobDesc& jd, uint32_t lt) {
     const uint64_t rest = jd.m - g.i0;
     g.bo = rest < jd.Bo ? rest : jd.Bo;
     g.sigma = g.i0 + jd.n - hi;
-    g.dst = (jd.nchunks > 1 ? jd.stage + (uint64_t)b * jd.out_words : jd.out) + (g.i0 >> 6);
+    g.dst = jd.out + (g.i0 >> 6);
     g.dst_words = (g.bo + 63) >> 6;
+    g.accumulate = jd.nchunks > 1;
+    g.clears = g.accumulate && b == 0;
     return g;
+}
+
+// Pass 1 of a chunk-0 tile of an accumulated job clears the window's words;
+// `part` of `parts` workgroups of the tile take an interleaved share.
+__device__ __forceinline__ void clear_window(const TileGeo& g, uint32_t part, uint32_t parts, int tid, int nthreads) {
+    if (!g.clears) return;
+    for (uint64_t w = (uint64_t)part * nthreads + tid; w < g.dst_words; w += (uint64_t)parts * nthreads) g.dst[w] = 0;
+}
+
+// Write B output bits at bit offset `off` (a multiple of B) of the window:
+// a plain store, or an XOR into the 32-bit word holding them when the job
+// accumulates chunks (zero groups are skipped).
+template <int B>
+__device__ __forceinline__ void put_bits(const TileGeo& g, uint64_t off, uint32_t bits) {
+    static_assert(B == 8 || B == 16 || B == 32, "bit group");
+    if (g.accumulate) {
+        if (bits) atomicXor(reinterpret_cast<uint32_t*>(g.dst) + (off >> 5), B == 32 ? bits : bits << (off & 31));
+    } else if constexpr (B == 32) {
+        reinterpret_cast<uint32_t*>(g.dst)[off >> 5] = bits;
+    } else if constexpr (B == 16) {
+        reinterpret_cast<uint16_t*>(g.dst)[off >> 4] = (uint16_t)bits;
+    } else {
+        reinterpret_cast<uint8_t*>(g.dst)[off >> 3] = (uint8_t)bits;
+    }
 }
 
 template <typename T>
@@ -89,6 +117,7 @@ k_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part,
     const int tid = threadIdx.x, f = tid % B, j = tid / B;
     const uint32_t t1 = cb * B + f;
     if (tid == 0) wsum = 0;
+    clear_window(g, cb, NCB, tid, B * (N2 / R));
 
     const uint32_t bi = (uint32_t)g.bi, win = (uint32_t)(g.bi + g.bo - 1);
     uint32_t pc = 0;
@@ -246,14 +275,6 @@ template <typename T> __device__ __forceinline__ T round_even(T z);
 template <> __device__ __forceinline__ float round_even<float>(float z) { return rintf(z); }
 template <> __device__ __forceinline__ double round_even<double>(double z) { return rint(z); }
 
-template <int B> __device__ __forceinline__ void store_group(uint64_t* dst, uint64_t off, uint32_t bits);
-template <> __device__ __forceinline__ void store_group<8>(uint64_t* dst, uint64_t off, uint32_t bits) {
-    reinterpret_cast<uint8_t*>(dst)[off >> 3] = (uint8_t)bits;
-}
-template <> __device__ __forceinline__ void store_group<16>(uint64_t* dst, uint64_t off, uint32_t bits) {
-    reinterpret_cast<uint16_t*>(dst)[off >> 4] = (uint16_t)bits;
-}
-
 template <typename T, int N1, int N2, int B, int R>
 __global__ void __launch_bounds__(B * (N2 / 2 / R))
 k_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta, const cx<T>* __restrict__ tw) {
@@ -315,8 +336,7 @@ k_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta, 
             const uint64_t mask = __ballot(bit);
             if (f == 0) {
                 const uint64_t off = (uint64_t)cb * B + (uint64_t)N1 * t2;
-                if (off < g.dst_words * 64u)
-                    store_group<B>(g.dst, off, (uint32_t)(mask >> lane) & ((1u << B) - 1u));
+                if (off < g.dst_words * 64u) put_bits<B>(g, off, (uint32_t)(mask >> lane) & ((1u << B) - 1u));
             }
         }
     }

@@ -135,6 +135,7 @@ k2_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const
     const int tid = threadIdx.x;
     const uint32_t bi = (uint32_t)g.bi, win = (uint32_t)(g.bi + g.bo - 1);
     if (tid == 0) wsum = 0;
+    clear_window(g, cb, NCB, tid, Gm::THREADS);
     wfft_load_lds<T, M>(st, stw, tid, Gm::THREADS);
     __syncthreads();
 
@@ -628,9 +629,7 @@ k2_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta,
         }
         const uint64_t off = (uint64_t)cb * C + 32u * c + (uint64_t)kN1 * t2;
         if (off >= limit) continue;
-        if constexpr (C >= 32) reinterpret_cast<uint32_t*>(g.dst)[off >> 5] = word;
-        else if constexpr (C == 16) reinterpret_cast<uint16_t*>(g.dst)[off >> 4] = (uint16_t)word;
-        else reinterpret_cast<uint8_t*>(g.dst)[off >> 3] = (uint8_t)word;
+        put_bits<WB>(g, off, word);
     }
     if (tid == 0) {
         atomicMax(&meta[t].maxres, s_res);

@@ -202,7 +202,6 @@ void Lane::release(Ctx* c) {
     part.release(c);
     meta.release(c);
     jobs_dev.release(c);
-    stage.release(c);
     io.release(c);
     meta_host.release();
     jobs_host.release();
@@ -238,28 +237,16 @@ pa_status Lane::launch(Ctx* c, int prec_, int logL_, std::vector<JobDesc>& js, b
     prec = prec_;
     logL = logL_;
     const ClassCfg& cfg = K->cfg;
+    // Tiles in job order; within a job chunk 0 comes first, so a window is
+    // cleared (pass 1 of its chunk-0 tile) before any chunk XORs into it, also
+    // when the tiles are split over several launches.
     uint32_t total = 0;
-    uint64_t stage_words = 0, max_words = 0;
     for (JobDesc& jd : js) {
         jd.tile_begin = total;
         total += jd.nchunks * jd.nouts;
-        if (jd.nchunks > 1) {
-            stage_words += (uint64_t)jd.nchunks * jd.out_words;
-            max_words = std::max<uint64_t>(max_words, jd.out_words);
-        }
     }
-    pa_status st = stage.ensure(c, std::max<uint64_t>(stage_words, 1) * 8);
-    if (st != PA_OK) return st;
-    uint64_t off = 0;
-    for (JobDesc& jd : js)
-        if (jd.nchunks > 1) {
-            jd.stage = (uint64_t*)stage.ptr + off;
-            off += (uint64_t)jd.nchunks * jd.out_words;
-        } else {
-            jd.stage = nullptr;
-        }
     Tables tb;
-    st = c->tables(prec, logL, &tb);
+    pa_status st = c->tables(prec, logL, &tb);
     if (st != PA_OK) return st;
     st = meta.ensure(c, (size_t)total * sizeof(TileMeta));
     if (st != PA_OK) return st;
@@ -306,14 +293,6 @@ pa_status Lane::launch(Ctx* c, int prec_, int logL_, std::vector<JobDesc>& js, b
     if (timing) timer.reset();
     st = run_passes(K, jt, 0, total, G, this, tb, timing, &stats->launches);
     if (st != PA_OK) return st;
-    if (max_words) {
-        jt.tile0 = 0;
-        jt.ntiles = total;
-        hipEvent_t a = timing ? timer.mark(stream) : nullptr;
-        if (launch_merge(jt, max_words, stream)) return PA_EDEVICE;
-        if (timing) timer.spans.push_back({3, {a, timer.mark(stream)}});
-        stats->launches += 1;
-    }
     if (fetch_meta) {
         st = meta_host.ensure((size_t)total * sizeof(TileMeta));
         if (st != PA_OK) return st;
@@ -367,8 +346,9 @@ pa_status Lane::finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_s
             for (uint32_t t : failed) (*per_job)[job_of(t)] = PA_EPRECISION;
         return PA_EPRECISION;
     }
-    // Re-run each failed tile in FP64 (same geometry and length class) into
-    // the same output words, then re-merge its job.
+    // Re-run in FP64 with the same geometry and length class: a failed tile of
+    // a one-chunk job alone (its window is overwritten); every tile of a job
+    // that accumulates chunks (its windows are cleared and rebuilt).
     Tables tb;
     pa_status st = c->tables(PREC_FP64, logL, &tb);
     if (st != PA_OK) return st;
@@ -376,41 +356,45 @@ pa_status Lane::finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_s
     if (st != PA_OK) return st;
     st = part.ensure(c, (size_t)(K64->cfg.n1 / K64->cfg.b1) * sizeof(uint32_t));
     if (st != PA_OK) return st;
-    std::vector<uint8_t> remerge(jobs.size(), 0);
-    pa_status result = PA_OK;
+    std::vector<uint8_t> whole(jobs.size(), 0);
+    std::vector<std::pair<size_t, uint32_t>> runs;   // (job, local tile); local = ~0u: all tiles
     for (uint32_t t : failed) {
         const size_t jx = job_of(t);
-        const uint32_t local = t - jobs[jx].tile_begin;
+        if (jobs[jx].nchunks > 1) {
+            if (!whole[jx]) runs.push_back({jx, ~0u});
+            whole[jx] = 1;
+        } else {
+            runs.push_back({jx, t - jobs[jx].tile_begin});
+        }
+    }
+    pa_status result = PA_OK;
+    for (const auto& r : runs) {
+        const size_t jx = r.first;
+        const uint32_t ntiles = jobs[jx].nchunks * jobs[jx].nouts;
+        const uint32_t first = r.second == ~0u ? 0u : r.second, end = r.second == ~0u ? ntiles : r.second + 1;
         JobTable jt{};
         jt.one = jobs[jx];
         jt.one.tile_begin = 0;
         jt.njobs = 0;
-        st = meta.ensure(c, (size_t)(local + 1) * sizeof(TileMeta));
+        st = meta.ensure(c, (size_t)end * sizeof(TileMeta));
         if (st != PA_OK) return st;
-        st = run_passes(K64, jt, local, local + 1, 1, this, tb, false, &stats->launches);
+        st = run_passes(K64, jt, first, end, 1, this, tb, false, &stats->launches);
         if (st != PA_OK) return st;
-        stats->fallback_tiles += 1;
-        stats->tiles += 1;
-        TileMeta m64;
-        if (hipMemcpyAsync(&m64, (TileMeta*)meta.ptr + local, sizeof(TileMeta), hipMemcpyDeviceToHost, stream) !=
-                hipSuccess ||
+        stats->fallback_tiles += end - first;
+        stats->tiles += end - first;
+        std::vector<TileMeta> m64(end - first);
+        if (hipMemcpyAsync(m64.data(), (TileMeta*)meta.ptr + first, (end - first) * sizeof(TileMeta),
+                           hipMemcpyDeviceToHost, stream) != hipSuccess ||
             hipStreamSynchronize(stream) != hipSuccess)
             return PA_EDEVICE;
-        double r, a;
-        if (!tile_ok(PREC_FP64, m64, &r, &a)) {
-            result = PA_EPRECISION;
-            if (per_job) (*per_job)[jx] = PA_EPRECISION;
+        for (const TileMeta& m : m64) {
+            double rr, aa;
+            if (!tile_ok(PREC_FP64, m, &rr, &aa)) {
+                result = PA_EPRECISION;
+                if (per_job) (*per_job)[jx] = PA_EPRECISION;
+            }
         }
-        if (jobs[jx].nchunks > 1) remerge[jx] = 1;
     }
-    for (size_t jx = 0; jx < jobs.size(); ++jx)
-        if (remerge[jx]) {
-            JobTable jt{};
-            jt.one = jobs[jx];
-            jt.njobs = 0;
-            if (launch_merge(jt, jobs[jx].out_words, stream)) return PA_EDEVICE;
-            stats->launches += 1;
-        }
     if (hipStreamSynchronize(stream) != hipSuccess) return PA_EDEVICE;
     return result;
 }

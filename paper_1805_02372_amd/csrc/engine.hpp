@@ -56,7 +56,7 @@ struct Lane {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     uint64_t cap = 0;     // workspace cap in bytes (0: the context budget)
-    DevBuf ws, part, meta, jobs_dev, stage, io;
+    DevBuf ws, part, meta, jobs_dev, io;
     HostBuf meta_host, jobs_host;
     PassTimer timer;
 
@@ -68,13 +68,14 @@ struct Lane {
 
     void release(Ctx* c);
 
-    // Enqueue every tile of `jobs` (planned at class prec/logL) and the merge;
-    // sets tile_begin and stage pointers.  With `fetch_meta` the tile
+    // Enqueue every tile of `jobs` (planned at class prec/logL); sets
+    // tile_begin.  With `fetch_meta` the tile
     // certificates are copied to meta_host behind the kernels.
     pa_status launch(Ctx* c, int prec, int logL, std::vector<JobDesc>& jobs, bool timing, bool fetch_meta,
                      pa_stats* stats);
     // After the launch completed: check certificates, re-run failed FP32
-    // tiles in FP64, re-merge.  Synchronous on this lane's stream.
+    // tiles (whole jobs when they accumulate chunks) in FP64.  Synchronous on
+    // this lane's stream.
     pa_status finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_status>* per_job);
 };
 

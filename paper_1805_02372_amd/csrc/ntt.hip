@@ -154,6 +154,7 @@ k_ntt1(JobTable jt, uint32_t* __restrict__ ws, uint32_t* __restrict__ part, Root
     const uint32_t t1 = cb * kB1 + col;
     const uint32_t bi = (uint32_t)g.bi, win = (uint32_t)(g.bi + g.bo - 1);
     if (tid == 0) wsum = 0;
+    clear_window(g, cb, NCB, tid, 2 * kB1 * (N2 / kR));
     __syncthreads();
     uint32_t v[kR];
     uint32_t pc = 0;
@@ -274,8 +275,7 @@ k_ntt3(JobTable jt, const uint32_t* __restrict__ ws, TileMeta* __restrict__ meta
         const uint64_t mask = __ballot(bit);
         if (f == 0) {
             const uint64_t off = (uint64_t)cb * kB3 + (uint64_t)N1 * t2;
-            if (off < g.dst_words * 64u)
-                reinterpret_cast<uint8_t*>(g.dst)[off >> 3] = (uint8_t)((mask >> lane) & 0xFFu);
+            if (off < g.dst_words * 64u) put_bits<8>(g, off, (uint32_t)((mask >> lane) & 0xFFu));
         }
     }
     __syncthreads();

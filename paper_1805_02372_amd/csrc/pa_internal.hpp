@@ -9,6 +9,9 @@ namespace pa {
 // (taken from the top of the key: chunk b covers key bits
 // [max(0, n-(b+1)Bi), n-b*Bi)) and `nouts` output windows (window o covers
 // outputs [o*Bo, min(m, (o+1)*Bo))); tile (b, o) is local tile b*nouts + o.
+// With several chunks the tiles' partial hashes are XOR-accumulated into
+// `out` (Eq. 7): pass 1 of the chunk-0 tile clears its window's words, pass 3
+// of every tile XORs its bits in.
 // Tile (b, o) with chunk start j0, length bi, window start i0, length bo uses
 // seed bits [sigma, sigma+bi+bo-1) with sigma = i0 - j0 + n - bi: by the
 // constant diagonals of T its outputs are the window [bi-1, bi-1+bo) of the
@@ -17,7 +20,6 @@ struct JobDesc {
     const uint64_t* key;
     const uint64_t* seed;
     uint64_t* out;        // m bits
-    uint64_t* stage;      // nchunks rows of out_words words (nchunks > 1), else null
     uint64_t n, m;
     uint64_t Bi, Bo;      // nominal chunk and window lengths (Bo % 64 == 0 if nouts > 1)
     uint32_t nchunks, nouts;
@@ -73,7 +75,6 @@ struct ClassKernels {
 
 // Registered by the per-precision kernel objects.
 const ClassKernels* class_kernels(int prec, int logL);
-int launch_merge(const JobTable& jt, uint64_t max_words, void* stream);
 
 constexpr int kMinLogL = 12;
 constexpr int kMaxLogL32 = 24;

@@ -226,7 +226,6 @@ pa_status pa_submit(pa_ctx* ctx, uint32_t seed_id, uint64_t n, uint64_t m, const
             for (Lane* ln : direct) {
                 ln->ws.release(c);
                 ln->part.release(c);
-                ln->stage.release(c);
             }
         }
         std::vector<Lane> lanes(serve_lanes());
