@@ -126,6 +126,31 @@ def test_fp32_certificate_falls_back_on_all_ones_seed(pa, ctx):
     assert st2 == pa.PA_EPRECISION
 
 
+def test_fallback_rebuilds_accumulated_job(pa, ctx, monkeypatch):
+    """With the class capped at 2^21 the job is cut into key chunks whose
+    partial hashes are XOR-accumulated.  With an all-ones key and seed every
+    window value equals the chunk length (> 2^20), so every FP32 tile fails
+    its certificate and the whole job is rebuilt in FP64.  Closed form: every
+    output is n mod 2.  A random job in the same batch keeps its FP32 result."""
+    from gpu_util import to_dev, from_dev, empty_dev
+    monkeypatch.setenv("PA_MAX_LOG2_LEN", "21")
+    rng = np.random.default_rng(22)
+    n, m = 3_000_001, 300_000
+    seed = synth.pattern_bits("ones", n + m - 1)
+    key = synth.pattern_bits("ones", n)
+    p2 = synth.random_problem(rng, 2_500_000, 250_000)
+    jobs = [(to_dev(seed), to_dev(key), empty_dev((m + 63) // 64), n, m),
+            (to_dev(p2.seed), to_dev(p2.key), empty_dev((p2.m + 63) // 64), p2.n, p2.m)]
+    st, per = pa.pa_hash_batch(ctx, jobs, pa.PA_PREC_FP32_SEG)
+    assert st == pa.PA_OK and per == [pa.PA_OK, pa.PA_OK]
+    s = pa.pa_last_stats(ctx)
+    plan = pa.pa_plan_query(n, m, pa.PA_PREC_FP32_SEG)
+    assert plan["chunks"] > 1, plan
+    assert s["fallback_tiles"] >= 2, s   # every tile of the all-ones job
+    assert np.array_equal(synth.bits_to_array(from_dev(jobs[0][2]), m), np.ones(m, np.uint8))
+    assert np.array_equal(from_dev(jobs[1][2]), oracle.hash_words(p2.seed, p2.n, p2.m, p2.key))
+
+
 @pytest.mark.parametrize("kind", ["period3", "block", "sparse"])
 def test_structured_inputs_exact(pa, ctx, kind):
     """Structured seeds and keys (where FP32 error is largest) stay exact
