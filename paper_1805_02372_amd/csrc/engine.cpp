@@ -89,6 +89,28 @@ void HostBuf::release() {
 
 // ------------------------------------------------------------ twiddle tables
 
+bool Ctx::plan_cached(uint64_t n, uint64_t m, int policy, TilePlan* out) {
+    const auto key = std::make_tuple(n, m, policy, min_logL(policy), max_logL(policy));
+    {
+        std::lock_guard<std::mutex> lk(plan_mu);
+        auto it = plans.find(key);
+        if (it != plans.end()) {
+            *out = it->second;
+            return true;
+        }
+    }
+    CostModel cm;
+    {
+        std::lock_guard<std::mutex> lk(plan_mu);
+        cm = cost;
+    }
+    if (!plan_job(n, m, policy, cm, out)) return false;
+    std::lock_guard<std::mutex> lk(plan_mu);
+    if (plans.size() >= 256) plans.clear();
+    plans[key] = *out;
+    return true;
+}
+
 pa_status Ctx::tables(int prec, int logL, Tables* out) {
     std::lock_guard<std::mutex> lk(tab_mu);
     const int key = prec * 100 + logL;
@@ -318,8 +340,20 @@ static bool tile_ok(int prec, const TileMeta& mt, double* res, double* mabs) {
     return std::isfinite(r) && std::isfinite(a) && r <= 0.125f && a < abs_limit && mt.badpar == 0;
 }
 
+// Wait for an event: poll for up to about 2 ms (a tile pipeline usually ends
+// well within that and polling avoids the wake-up latency of a blocking
+// wait), then block.
+static hipError_t wait_event(hipEvent_t e) {
+    const double t0 = now_seconds();
+    for (;;) {
+        const hipError_t q = hipEventQuery(e);
+        if (q != hipErrorNotReady) return q;
+        if (now_seconds() - t0 > 2e-3) return hipEventSynchronize(e);
+    }
+}
+
 pa_status Lane::finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_status>* per_job) {
-    if (hipEventSynchronize(done) != hipSuccess) return PA_EDEVICE;
+    if (wait_event(done) != hipSuccess) return PA_EDEVICE;
     if (flags & PA_TIMING) timer.collect(stats->ms_pass);
     const uint32_t total = total_tiles;
     const TileMeta* mt = (const TileMeta*)meta_host.ptr;
@@ -489,7 +523,7 @@ pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, con
     Lane& ln = c->main;
     pa_stats st{};
     TilePlan plan;
-    if (!plan_job(n, m, policy, c->cost, &plan)) return PA_EINVAL;
+    if (!c->plan_cached(n, m, policy, &plan)) return PA_EINVAL;
     fill_plan_stats(&st, plan);
 
     const uint64_t sw = words_of(n + m - 1), kw = words_of(n), ow = words_of(m);

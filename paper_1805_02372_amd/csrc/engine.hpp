@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "pa.h"
@@ -101,6 +102,11 @@ struct Ctx {
     std::vector<Lane> side;   // extra streams for the length-class groups of a batch
     std::map<int, DevTables> tabs;
     CostModel cost;
+    // Plans of recent single-job shapes (key: n, m, policy and the class
+    // limits in force); cleared when the cost model changes.
+    std::mutex plan_mu;
+    std::map<std::tuple<uint64_t, uint64_t, int, int, int>, TilePlan> plans;
+    bool plan_cached(uint64_t n, uint64_t m, int policy, TilePlan* out);
     pa_stats last{};
 
     pa_status tables(int prec, int logL, Tables* out);

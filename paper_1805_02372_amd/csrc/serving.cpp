@@ -56,9 +56,9 @@ void Ctx::serving_release() {
 // resident at once; a launch runs fewer at a time if the budget is short).
 // Workspace bytes of a request's cheapest FP32 plan (all tiles resident) and
 // of one of its tiles; the plan's length class goes to *cls.
-static uint64_t request_bytes(const CostModel& cm, uint64_t n, uint64_t m, uint64_t* min_bytes, int* cls) {
+static uint64_t request_bytes(Ctx* c, uint64_t n, uint64_t m, uint64_t* min_bytes, int* cls) {
     TilePlan p;
-    if (!plan_job(n, m, PREC_FP32, cm, &p)) {
+    if (!c->plan_cached(n, m, PREC_FP32, &p)) {
         *min_bytes = ~0ull;
         *cls = 0;
         return ~0ull;
@@ -119,7 +119,7 @@ void Ctx::serve_loop() {
                 ++scanned;
                 uint64_t bmin = 0;
                 int cls = 0;
-                const uint64_t b = request_bytes(cost, r->n, r->m, &bmin, &cls);
+                const uint64_t b = request_bytes(this, r->n, r->m, &bmin, &cls);
                 if (bmin > budget) {
                     r->status = PA_ENOMEM;
                     r->t_done = now_seconds();
@@ -145,10 +145,15 @@ void Ctx::serve_loop() {
             }
             lk.unlock();
             const int logL = cls0;
+            CostModel cm;
+            {
+                std::lock_guard<std::mutex> pl(plan_mu);
+                cm = cost;
+            }
             std::vector<TilePlan> plans(batch.size());
             pa_status s = PA_OK;
             for (size_t k = 0; k < batch.size() && s == PA_OK; ++k)
-                if (!plan_at_class(ns[k], ms[k], PREC_FP32, logL, cost, &plans[k])) s = PA_EINVAL;
+                if (!plan_at_class(ns[k], ms[k], PREC_FP32, logL, cm, &plans[k])) s = PA_EINVAL;
             std::vector<JobDesc> jobs(batch.size());
             if (s == PA_OK) {
                 for (size_t k = 0; k < batch.size(); ++k)

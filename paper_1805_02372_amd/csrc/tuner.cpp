@@ -125,12 +125,17 @@ pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path) {
         buf.release(c);
         return PA_EDEVICE;
     }
+    CostModel cm;
+    {
+        std::lock_guard<std::mutex> lk(c->plan_mu);
+        cm = c->cost;
+    }
     std::vector<double> fixed;
     for (int prec : precs)
         for (int k = 12; k <= 24; ++k) {
             const uint64_t L = 1ull << k;
             TilePlan p;
-            if (!plan_at_class(L / 2, L / 2 + 1, prec, k, c->cost, &p) || p.tiles() != 1) continue;
+            if (!plan_at_class(L / 2, L / 2 + 1, prec, k, cm, &p) || p.tiles() != 1) continue;
             double t1 = 0, t4 = 0;
             st = time_launch(c, prec, k, p, 1, dseed, dkey, douts, out_words, reps, &t1);
             if (st == PA_OK) st = time_launch(c, prec, k, p, kMany, dseed, dkey, douts, out_words, reps, &t4);
@@ -140,19 +145,33 @@ pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path) {
             }
             if (t1 >= 1e30 || t4 >= 1e30) continue;
             const double marginal = std::max((t4 - t1) / (kMany - 1), 0.1 * t1);
-            c->cost.set(prec, k, marginal);
+            cm.set(prec, k, marginal);
             fixed.push_back(std::max(t1 - marginal, 0.0));
         }
     buf.release(c);
     if (!fixed.empty()) {
         std::sort(fixed.begin(), fixed.end());
-        c->cost.launch_s = fixed[fixed.size() / 2];
+        cm.launch_s = fixed[fixed.size() / 2];
     }
-    if (path) return save_json(c->cost, precs, path);
+    {
+        std::lock_guard<std::mutex> lk(c->plan_mu);
+        c->cost = cm;
+        c->plans.clear();
+    }
+    if (path) return save_json(cm, precs, path);
     return PA_OK;
 }
 
-pa_status tune_load(Ctx* c, const char* path) { return load_json(c->cost, path); }
+pa_status tune_load(Ctx* c, const char* path) {
+    std::lock_guard<std::mutex> lk(c->plan_mu);
+    CostModel cm = c->cost;
+    const pa_status st = load_json(cm, path);
+    if (st == PA_OK) {
+        c->cost = cm;
+        c->plans.clear();
+    }
+    return st;
+}
 
 }  // namespace pa
 
