@@ -281,11 +281,18 @@ __device__ __forceinline__ void row_smem_load(RowSmem<T>& S, const cx<T>* __rest
     }
 }
 
-// 1024-point wave transform of the row pass, stage tables from LDS or global
+// Last-stage twiddles of the 1024-point transform held in registers for the
+// whole row pass (FP32): w_1024^{l r}, r = 1..15.
+template <typename T> struct RowReg {
+    cx<T> tr[RowSmem<T>::kLds ? 15 : 1];
+};
+
+// 1024-point wave transform of the row pass, stage tables from LDS (and
+// registers) or global
 template <typename T, int DIR>
 __device__ __forceinline__ void row_wave_fft(cx<T> (&v)[16], cx<T>* __restrict__ reg, int l, const RowSmem<T>& S,
-                                             const cx<T>* __restrict__ stw) {
-    if constexpr (RowSmem<T>::kLds) wave_fft_lds<T, DIR, 1024>(v, reg, l, S.st);
+                                             const RowReg<T>& R, const cx<T>* __restrict__ stw) {
+    if constexpr (RowSmem<T>::kLds) wave_fft1024_lds_reg<T, DIR>(v, reg, l, S.st, R.tr);
     else wave_fft<T, DIR, 1024>(v, reg, l, stw);
 }
 
@@ -309,8 +316,9 @@ __device__ __forceinline__ void row_load(cx<T> (&a)[16], const cx<T>* __restrict
 // Forward transform of one 8192-point row loaded by row_load (a is consumed).
 // Thread (wave w, lane l) ends with X[8 k_b + w] in register i, k_b = l + 64 i.
 template <typename T>
-__device__ __forceinline__ void row_forward(cx<T> (&a)[16], cx<T> (&X)[16], RowSmem<T>& S, int wv, int l,
-                                            const cx<T>* __restrict__ tw, const cx<T>* __restrict__ stw) {
+__device__ __forceinline__ void row_forward(cx<T> (&a)[16], cx<T> (&X)[16], RowSmem<T>& S, const RowReg<T>& R,
+                                            int wv, int l, const cx<T>* __restrict__ tw,
+                                            const cx<T>* __restrict__ stw) {
     constexpr int SS = kWaveSlots;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -331,18 +339,19 @@ __device__ __forceinline__ void row_forward(cx<T> (&a)[16], cx<T> (&X)[16], RowS
 #pragma unroll
     for (int i = 0; i < 16; ++i) X[i] = reg[wslot(l + 64 * i)];
     wave_sync();
-    row_wave_fft<T, -1>(X, reg, l, S, stw);
+    row_wave_fft<T, -1>(X, reg, l, S, R, stw);
 }
 
 // Inverse transform of a row held as P[8 k_b + w] (register i, k_b = l + 64 i);
 // returns a[t_b + 1024 t_a] in a[s * 8 + t_a] for t_b = w * 64 + l + 512 s.
 template <typename T>
-__device__ __forceinline__ void row_inverse(cx<T> (&P)[16], cx<T> (&a)[16], RowSmem<T>& S, int wv, int l,
-                                            const cx<T>* __restrict__ tw, const cx<T>* __restrict__ stw) {
+__device__ __forceinline__ void row_inverse(cx<T> (&P)[16], cx<T> (&a)[16], RowSmem<T>& S, const RowReg<T>& R,
+                                            int wv, int l, const cx<T>* __restrict__ tw,
+                                            const cx<T>* __restrict__ stw) {
     constexpr int SS = kWaveSlots;
     cx<T>* reg = S.data + wv * SS;
     __syncthreads();  // every wave is done with its region
-    row_wave_fft<T, +1>(P, reg, l, S, stw);
+    row_wave_fft<T, +1>(P, reg, l, S, R, stw);
     if (wv > 0) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) P[i] = cmulc(P[i], w8192<T>(S, tw, wv, l + 64 * i));
@@ -423,7 +432,8 @@ template <typename T> constexpr bool kRowPersistent = sizeof(T) == 4;
 template <typename T, int N2, int NCB1>
 __device__ __forceinline__ void row_unit(uint32_t u, const JobTable& jt, cx<T>* __restrict__ ws,
                                          const uint32_t* __restrict__ part, TileMeta* __restrict__ meta,
-                                         RowSmem<T>& S, uint32_t& wsum, const cx<T>* __restrict__ tw,
+                                         RowSmem<T>& S, const RowReg<T>& R, uint32_t& wsum,
+                                         const cx<T>* __restrict__ tw,
                                          const cx<T>* __restrict__ stw, const cx<double>* __restrict__ fa64,
                                          const cx<double>* __restrict__ fb64, int fshift) {
     constexpr uint32_t L = (uint32_t)kN1 * N2;
@@ -442,13 +452,13 @@ __device__ __forceinline__ void row_unit(uint32_t u, const JobTable& jt, cx<T>* 
         cx<T> ra[16], rb[16], A[16], B[16], a[16];
         row_load<T>(ra, Y + (size_t)pr * kN1, wv, l);
         if constexpr (kHoist) row_load<T>(rb, Y + (size_t)(N2 - pr) * kN1, wv, l);
-        row_forward<T>(ra, A, S, wv, l, tw, stw);
+        row_forward<T>(ra, A, S, R, wv, l, tw, stw);
         if constexpr (!kHoist) row_load<T>(rb, Y + (size_t)(N2 - pr) * kN1, wv, l);
-        row_forward<T>(rb, B, S, wv, l, tw, stw);
+        row_forward<T>(rb, B, S, R, wv, l, tw, stw);
         row_mirror<T>(B, S.data, wv, l, false);
 #pragma unroll
         for (int i = 0; i < 16; ++i) A[i] = spectrum_product(A[i], B[i], quarter);
-        row_inverse<T>(A, a, S, wv, l, tw, stw);
+        row_inverse<T>(A, a, S, R, wv, l, tw, stw);
         row_store<T>(Y + (size_t)pr * kN1, a, pr, false, wv, l, fa64, fb64, fshift);
     } else {
         // key-chunk weight from the pass-1 partial sums; reset the certificate
@@ -467,13 +477,13 @@ __device__ __forceinline__ void row_unit(uint32_t u, const JobTable& jt, cx<T>* 
             const uint32_t row = v == 0 ? 0u : (uint32_t)NP;
             cx<T> ra[16], A[16], B[16], a[16];
             row_load<T>(ra, Y + (size_t)row * kN1, wv, l);
-            row_forward<T>(ra, A, S, wv, l, tw, stw);
+            row_forward<T>(ra, A, S, R, wv, l, tw, stw);
 #pragma unroll
             for (int i = 0; i < 16; ++i) B[i] = A[i];
             row_mirror<T>(B, S.data, wv, l, v == 0);
 #pragma unroll
             for (int i = 0; i < 16; ++i) A[i] = spectrum_product(A[i], B[i], quarter);
-            row_inverse<T>(A, a, S, wv, l, tw, stw);
+            row_inverse<T>(A, a, S, R, wv, l, tw, stw);
             row_store<T>(Y + (size_t)row * kN1, a, row, true, wv, l, fa64, fb64, fshift);
         }
     }
@@ -488,12 +498,19 @@ k2_pass2(JobTable jt, cx<T>* __restrict__ ws, const uint32_t* __restrict__ part,
     __shared__ uint32_t wsum;
     const uint32_t units = jt.ntiles * (uint32_t)(N2 / 2);
     row_smem_load<T>(S, tw, stw, threadIdx.x);
+    RowReg<T> R;
+    if constexpr (RowSmem<T>::kLds) {
+        // w_1024^{l r} = w_8192^{8 l r}, l r < 1024
+        const int l = threadIdx.x & 63;
+#pragma unroll
+        for (int r = 1; r < 16; ++r) R.tr[r - 1] = tw[8 * l * r];
+    }
     if constexpr (kRowPersistent<T>) {
         for (uint32_t u = blockIdx.x; u < units; u += gridDim.x)
-            row_unit<T, N2, NCB1>(u, jt, ws, part, meta, S, wsum, tw, stw, fa64, fb64, fshift);
+            row_unit<T, N2, NCB1>(u, jt, ws, part, meta, S, R, wsum, tw, stw, fa64, fb64, fshift);
     } else {
         if (blockIdx.x < units)
-            row_unit<T, N2, NCB1>(blockIdx.x, jt, ws, part, meta, S, wsum, tw, stw, fa64, fb64, fshift);
+            row_unit<T, N2, NCB1>(blockIdx.x, jt, ws, part, meta, S, R, wsum, tw, stw, fa64, fb64, fshift);
     }
 }
 

@@ -151,6 +151,25 @@ __device__ __forceinline__ void wave_fft(cx<T> (&v)[16], cx<T>* __restrict__ reg
     wfft_stages<T, DIR, M, 1, false>(v, reg, j, stw);
 }
 
+// 1024-point transform whose last stage (span 64) takes its twiddles from
+// registers: tr[r-1] = w_1024^{j r} (forward root) for this lane j; the
+// earlier stages read the LDS copy.
+template <typename T, int DIR>
+__device__ __forceinline__ void wave_fft1024_lds_reg(cx<T> (&v)[16], cx<T>* __restrict__ reg, int j, const cx<T>* st,
+                                                     const cx<T> (&tr)[15]) {
+    wfft_stage<T, DIR, 1024, 4, 1, true>(v, reg, j, st);
+    wfft_stage<T, DIR, 1024, 16, 4, true>(v, reg, j, st);
+    // last stage: span 64, radix 16, k = j
+    cx<T> u[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) u[r] = v[r];
+#pragma unroll
+    for (int r = 1; r < 16; ++r) u[r] = twmul<DIR>(u[r], tr[r - 1]);
+    dft<16, DIR>(u);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = u[r];
+}
+
 // The same with the size-M stage tables in LDS (wfft_load_lds).
 template <typename T, int DIR, int M>
 __device__ __forceinline__ void wave_fft_lds(cx<T> (&v)[16], cx<T>* __restrict__ reg, int j, const cx<T>* st) {
