@@ -184,7 +184,9 @@ def run_serving(pa, ctx, torch, count: int, load: float = 0.7):
         got = synth.bits_to_array(outs[int(k)].cpu().numpy().view(np.uint64), r["m"])[idx]
         exact = exact and bool(np.array_equal(ref, got))
     total_n = sum(r["n"] for r in reqs)
+    ss = pa.pa_serve_stats(ctx)
     return {"requests": len(reqs), "sustained_gbps": round(total_n / wall / 1e9, 3),
+            "tiles": ss["tiles"], "fallback_tiles": ss["fallback_tiles"],
             "offered_rate_per_s": round(rate, 1), "burst_capacity_gbps": round(cap / 1e9, 3),
             "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),

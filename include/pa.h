@@ -150,6 +150,11 @@ typedef struct {
 /* Statistics of the last pa_hash / pa_hash_batch on this context. */
 pa_status pa_last_stats(pa_ctx* ctx, pa_stats* stats);
 
+/* Statistics summed over the serving launches finished so far: tiles,
+ * fallback_tiles (FP32 tiles re-run in FP64), launches, model_bytes, and the
+ * largest max_residual / max_abs.  The plan fields are not set. */
+pa_status pa_serve_stats(pa_ctx* ctx, pa_stats* stats);
+
 /* Human-readable name of a status. */
 const char* pa_strerror(pa_status status);
 

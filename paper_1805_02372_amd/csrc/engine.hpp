@@ -120,6 +120,7 @@ struct Ctx {
     std::vector<uint64_t> seed_bits;
     std::vector<Lane> lanes;
     std::vector<std::vector<Request*>> lane_reqs;
+    pa_stats serve_total{};   // summed over the finished serving launches
     std::thread worker;
     bool stop = false, worker_started = false;
     uint64_t next_ticket = 1;

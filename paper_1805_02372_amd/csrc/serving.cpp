@@ -90,6 +90,15 @@ void Ctx::serve_loop() {
             pa_status s = lanes[i].finish(this, 0, &lane_stats[i], &per);
             const double t = now_seconds();
             lk.lock();
+            {
+                const pa_stats& x = lane_stats[i];
+                serve_total.tiles += x.tiles;
+                serve_total.fallback_tiles += x.fallback_tiles;
+                serve_total.launches += x.launches;
+                serve_total.model_bytes += x.model_bytes;
+                serve_total.max_residual = std::max(serve_total.max_residual, x.max_residual);
+                serve_total.max_abs = std::max(serve_total.max_abs, x.max_abs);
+            }
             for (size_t k = 0; k < reqs.size(); ++k) {
                 reqs[k]->status = (s == PA_OK || s == PA_EPRECISION) ? per[k] : s;
                 reqs[k]->t_done = t;
@@ -160,6 +169,7 @@ void Ctx::serve_loop() {
                     fill_job(&jobs[k], (const uint64_t*)seeds[batch[k]->seed_id].ptr, batch[k]->key, batch[k]->out,
                              batch[k]->n, batch[k]->m, plans[k]);
                 lane_stats[i] = pa_stats{};
+                for (const TilePlan& tp : plans) fill_plan_stats(&lane_stats[i], tp);
                 s = lanes[i].launch(this, PREC_FP32, logL, jobs, false, true, &lane_stats[i]);
             }
             lk.lock();
@@ -285,6 +295,14 @@ pa_status pa_wait(pa_ctx* ctx, uint64_t ticket) {
     Request* r = it->second;
     c->done_cv.wait(lk, [&] { return r->state == 2; });
     return r->status;
+}
+
+pa_status pa_serve_stats(pa_ctx* ctx, pa_stats* stats) {
+    if (!ctx || !stats) return PA_EINVAL;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    std::lock_guard<std::mutex> lk(c->smu);
+    *stats = c->serve_total;
+    return PA_OK;
 }
 
 pa_status pa_ticket_latency(pa_ctx* ctx, uint64_t ticket, double* seconds) {

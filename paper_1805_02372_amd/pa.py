@@ -87,6 +87,7 @@ _sig = {
     "pa_wait": (ctypes.c_int, [_P, ctypes.c_uint64]),
     "pa_ticket_latency": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]),
     "pa_last_stats": (ctypes.c_int, [_P, ctypes.POINTER(pa_stats)]),
+    "pa_serve_stats": (ctypes.c_int, [_P, ctypes.POINTER(pa_stats)]),
     "pa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "pa_plan_query": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(pa_plan)]),
     "pa_error_model": (ctypes.c_double, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64]),
@@ -208,6 +209,12 @@ def pa_ticket_latency(ctx, ticket: int) -> float:
 def pa_last_stats(ctx) -> dict:
     s = pa_stats()
     _check(_lib.pa_last_stats(ctx, ctypes.byref(s)), "pa_last_stats")
+    return s.as_dict()
+
+
+def pa_serve_stats(ctx) -> dict:
+    s = pa_stats()
+    _check(_lib.pa_serve_stats(ctx, ctypes.byref(s)), "pa_serve_stats")
     return s.as_dict()
 
 

@@ -226,9 +226,13 @@ def test_serving_mixed_stream_exact(pa, ctx):
     seeds = [synth.gen_bits(rng, seed_bits) for _ in range(2)]
     ids = [pa.pa_seed_register(ctx, to_dev(s), seed_bits) for s in seeds]
     reqs = _requests(rng, 40, seed_bits)
+    before = pa.pa_serve_stats(ctx)
     statuses, outs, lat = _serve(pa, ctx, reqs, None, ids)
     assert all(s == pa.PA_OK for s in statuses)
     assert all(x > 0 for x in lat)
+    after = pa.pa_serve_stats(ctx)
+    assert after["tiles"] > before["tiles"] and after["launches"] > before["launches"], after
+    assert after["max_residual"] < 0.125
     for r, y in zip(reqs, outs):
         sw = seeds[r["seed"]]
         st, alone = gpu_hash(pa, ctx, sw, r["n"], r["m"], r["key"], pa.PA_PREC_AUTO)
