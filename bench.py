@@ -124,56 +124,89 @@ def run_batch(pa, ctx, torch, jobs, flags, steps, warmup):
     return dict(elapsed=el, stats=pa.pa_last_stats(ctx), outs=outs)
 
 
-def run_serving(pa, ctx, torch, count: int, load: float = 0.7):
+def run_serving(pa, torch, count: int, load: float = 0.7, budget_gib: int = 8):
     """Serving workload: `count` requests, n log-uniform in [1e5, 1e8], m/n
     uniform in [0.02, 0.5], seeds = 8 resident 1.5e8-bit strings, Poisson
     arrivals.  Request keys are prefixes of 8 resident random 1e8-bit
     buffers (key k uses buffer k mod 8).  The arrival rate is `load` times the
-    capacity measured on a back-to-back burst of the same requests."""
+    capacity measured on a back-to-back burst of the same requests, on a
+    context of its own with an HBM budget of `budget_gib` GiB.  Beside the
+    main leg: a sweep of the load (0.5 and 0.9, 500 requests each) and the
+    same 500 requests at 0.7 under a 1 GiB budget, where admission binds."""
     import oracle
     import synth
     seeds, reqs = synth.serving_stream(count)
     rng = np.random.default_rng(5)
     keys = [synth.gen_bits(rng, 100_000_000) for _ in range(8)]
     dseeds = [torch.from_numpy(sd.view(np.int64).copy()).to("cuda:0") for sd in seeds]
-    sids = [pa.pa_seed_register(ctx, d, 150_000_000) for d in dseeds]
-    del dseeds
     dkeys = [torch.from_numpy(k.view(np.int64).copy()).to("cuda:0") for k in keys]
     outs = [torch.empty(((r["m"] + 63) // 64,), dtype=torch.int64, device="cuda:0") for r in reqs]
+    mean_n = float(np.mean([r["n"] for r in reqs]))
+    spacing = reqs[-1]["t"] / len(reqs)          # synth arrivals are at 100/s; rescaled below
 
-    def submit(k):
+    def new_ctx(gib):
+        c = pa.pa_create(0, gib << 30, None)
+        return c, [pa.pa_seed_register(c, d, 150_000_000) for d in dseeds]
+
+    def submit(c, sids, k):
         r = reqs[k]
-        st, t = pa.pa_submit(ctx, sids[r["seed_id"]], r["n"], r["m"], dkeys[k % 8], outs[k])
+        st, t = pa.pa_submit(c, sids[r["seed_id"]], r["n"], r["m"], dkeys[k % 8], outs[k])
         assert st == pa.PA_OK, pa.pa_strerror(st)
         return t
 
-    # capacity on a burst of the first requests
-    burst = list(range(min(64, count)))
-    a = time.perf_counter()
-    tk = [submit(k) for k in burst]
-    for t in tk:
-        st = pa.pa_wait(ctx, t)
-        assert st == pa.PA_OK, pa.pa_strerror(st)
-    cap = sum(reqs[k]["n"] for k in burst) / (time.perf_counter() - a)
-    mean_n = float(np.mean([r["n"] for r in reqs]))
-    rate = load * cap / mean_n
-    scale = (reqs[-1]["t"] / len(reqs)) * rate   # synth arrivals are at 100/s; rescale
-    torch.cuda.synchronize()
-    log(f"[bench] serving: capacity {cap / 1e9:.2f} Gbps on a burst, arrival rate {rate:.0f}/s")
-    t0 = time.perf_counter()
-    tickets = []
-    for k, r in enumerate(reqs):
-        due = t0 + r["t"] / scale
-        while True:
-            dt = due - time.perf_counter()
-            if dt <= 0:
-                break
-            time.sleep(min(dt, 0.002))
-        tickets.append(submit(k))
-    status = [pa.pa_wait(ctx, t) for t in tickets]
-    wall = time.perf_counter() - t0
-    assert all(s == pa.PA_OK for s in status), [pa.pa_strerror(s) for s in set(status)]
-    lat = np.array([pa.pa_ticket_latency(ctx, t) for t in tickets])
+    def play(c, sids, idx, rate):
+        t0 = time.perf_counter()
+        tickets = []
+        for k in idx:
+            due = t0 + (reqs[k]["t"] - reqs[idx[0]]["t"]) / (spacing * rate)
+            while True:
+                dt = due - time.perf_counter()
+                if dt <= 0:
+                    break
+                time.sleep(min(dt, 0.002))
+            tickets.append(submit(c, sids, k))
+        status = [pa.pa_wait(c, t) for t in tickets]
+        wall = time.perf_counter() - t0
+        assert all(s == pa.PA_OK for s in status), [pa.pa_strerror(s) for s in set(status)]
+        lat = np.array([pa.pa_ticket_latency(c, t) for t in tickets])
+        total_n = sum(reqs[k]["n"] for k in idx)
+        return {"requests": len(idx), "offered_rate_per_s": round(rate, 1),
+                "sustained_gbps": round(total_n / wall / 1e9, 3),
+                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3), "wall_s": round(wall, 3)}
+
+    ctx, sids = new_ctx(budget_gib)
+    try:
+        # capacity on a burst of the first requests
+        burst = list(range(min(64, count)))
+        a = time.perf_counter()
+        tk = [submit(ctx, sids, k) for k in burst]
+        for t in tk:
+            st = pa.pa_wait(ctx, t)
+            assert st == pa.PA_OK, pa.pa_strerror(st)
+        cap = sum(reqs[k]["n"] for k in burst) / (time.perf_counter() - a)
+        torch.cuda.synchronize()
+        log(f"[bench] serving: capacity {cap / 1e9:.2f} Gbps on a burst")
+        main = play(ctx, sids, list(range(count)), load * cap / mean_n)
+        ss = pa.pa_serve_stats(ctx)
+        main.update({"load": load, "hbm_budget_gib": budget_gib, "burst_capacity_gbps": round(cap / 1e9, 3),
+                     "tiles": ss["tiles"], "fallback_tiles": ss["fallback_tiles"]})
+        sub = list(range(min(500, count)))
+        sweep = []
+        for lf in (0.5, 0.9):
+            r = play(ctx, sids, sub, lf * cap / mean_n)
+            r["load"] = lf
+            sweep.append(r)
+            log(f"[bench] serving sweep: {r}")
+    finally:
+        pa.pa_destroy(ctx)
+    tctx, tsids = new_ctx(1)
+    try:
+        tight = play(tctx, tsids, sub, load * cap / mean_n)
+        tight.update({"load": load, "hbm_budget_gib": 1})
+        log(f"[bench] serving tight budget: {tight}")
+    finally:
+        pa.pa_destroy(tctx)
     # exactness spot check: 64 output bits of 8 requests, word-parallel oracle
     chk = np.random.default_rng(6).choice(len(reqs), size=min(8, len(reqs)), replace=False)
     exact = True
@@ -183,14 +216,10 @@ def run_serving(pa, ctx, torch, count: int, load: float = 0.7):
         ref = oracle.hash_select(seeds[r["seed_id"]], r["n"], r["m"], keys[int(k) % 8], idx)
         got = synth.bits_to_array(outs[int(k)].cpu().numpy().view(np.uint64), r["m"])[idx]
         exact = exact and bool(np.array_equal(ref, got))
-    total_n = sum(r["n"] for r in reqs)
-    ss = pa.pa_serve_stats(ctx)
-    return {"requests": len(reqs), "sustained_gbps": round(total_n / wall / 1e9, 3),
-            "tiles": ss["tiles"], "fallback_tiles": ss["fallback_tiles"],
-            "offered_rate_per_s": round(rate, 1), "burst_capacity_gbps": round(cap / 1e9, 3),
-            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-            "wall_s": round(wall, 3), "spot_check_exact": exact}
+    main["spot_check_exact"] = exact
+    main["sweep"] = sweep
+    main["tight_budget"] = tight
+    return main
 
 
 def cpu_baseline(prob, target_s: float = 12.0):
@@ -272,11 +301,7 @@ def main():
     serving = None
     if args.serve and not args.only:
         log(f"[bench] serving leg, {args.serve} requests")
-        sctx = pa.pa_create(0, 32 << 30, None)   # a serving process of its own: 32 GiB budget
-        try:
-            serving = run_serving(pa, sctx, torch, args.serve)
-        finally:
-            pa.pa_destroy(sctx)
+        serving = run_serving(pa, torch, args.serve)
         log(f"[bench] serving: {serving}")
 
     if args.calib_copy:

@@ -86,9 +86,31 @@ static double unit_roundoff(int prec) {
     return prec == PREC_FP32 ? std::ldexp(1.0, -24) : prec == PREC_FP64 ? std::ldexp(1.0, -53) : 0.0;
 }
 
+// Low-frequency term.  The key chunk is a 0/1 sequence on [0, Bi) padded with
+// zeros, so its mean (1/2 per bit) gives it the spectrum of a box,
+// |X_k| ~ D_k / 2 with the Dirichlet kernel D_k = |sin(pi Bi k / L) / sin(pi k / L)|,
+// which reaches L / (2 pi k) at the lowest frequencies.  With the two sequences
+// packed in one complex transform, an absolute error of about u |X_k| leaks
+// into the separated W_k, and the product picks up about u |X_k|^2 there.  The
+// inverse transform spreads these few bins over every output as a smooth
+// wave of rms u sqrt(sum_k 2 (D_k / 2)^4) / L; the sum converges like k^-4 and
+// 64 terms hold it.  The maximum over a tile is about 2-4 times the rms.
+static double box_leak_rms(int prec, int logL, uint64_t Bi) {
+    const double L = std::ldexp(1.0, logL);
+    const uint64_t twoL = 2ull << logL;
+    double s4 = 0;
+    for (uint64_t k = 1; k <= 64 && (double)k < L / 2; ++k) {
+        const uint64_t r = (Bi % twoL) * k % twoL;   // pi Bi k / L reduced mod 2 pi
+        const double d = std::fabs(std::sin(M_PI * (double)r / L) / std::sin(M_PI * (double)k / L)) / 2;
+        s4 += 2 * d * d * d * d;
+    }
+    return unit_roundoff(prec) * std::sqrt(s4) / L;
+}
+
 double error_bound(int prec, int logL, uint64_t Bi) {
     if (prec == PREC_NTT) return 0.0;
-    return 6.0 * g_kappa * unit_roundoff(prec) * std::sqrt((double)logL * (double)Bi);
+    return 6.0 * g_kappa * unit_roundoff(prec) * std::sqrt((double)logL * (double)Bi) +
+           5.0 * box_leak_rms(prec, logL, Bi);
 }
 
 double rigorous_bound(int prec, int logL, uint64_t Bi, uint64_t Bo) {
@@ -157,6 +179,7 @@ bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& 
     }
     if (!found) return false;
     best.bound = error_bound(prec, logL, best.Bi);
+    if (best.bound > kPlanErrorLimit) return false;   // not reached by FP32 up to 2^24
     best.cost = (double)best.tiles() * cm.tile(prec, logL) + cm.launch_s;
     *out = best;
     return true;

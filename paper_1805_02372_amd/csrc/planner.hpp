@@ -35,9 +35,12 @@ struct TilePlan {
     uint64_t tiles() const { return nchunks * nouts; }
 };
 
-// Probabilistic error model of one floating-point tile: about 6 standard
-// deviations of the output error for an FFT convolution of a +-1 sequence
-// with a 0/1 chunk of Bi bits at length 2^logL, sigma = kappa u sqrt(logL Bi).
+// Error model of one floating-point tile, a predicted maximum of the output
+// error for an FFT convolution of a +-1 sequence with a 0/1 chunk of Bi bits at
+// length 2^logL: 6 sigma of the random rounding noise, sigma = kappa u
+// sqrt(logL Bi), plus 5 times the rms of the low-frequency error that the
+// chunk's zero padding causes (about 0.036 u L once Bi > L/3; the larger term
+// from 2^22 on in FP32).
 double error_bound(int prec, int logL, uint64_t Bi);
 // Worst-case (a-priori) bound: ||x|| ||w|| times the relative error growth of
 // the FFT, product and inverse FFT, with ||x|| <= sqrt(Bi), ||w|| = sqrt(Bi+Bo-1).

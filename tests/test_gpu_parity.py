@@ -78,6 +78,8 @@ def test_forced_tiling(pa, ctx, cap, n, m, prec, monkeypatch):
     assert np.array_equal(y, ref), describe(y, ref, m) + f" plan {plan}"
     s = pa.pa_last_stats(ctx)
     assert s["tiles"] == plan["chunks"] * plan["windows"]
+    if prec == "fp32":
+        assert s["max_residual"] <= s["bound"], s   # the error model holds on random inputs
     assert plan["log2_len"] <= cap
 
 
@@ -113,6 +115,8 @@ def test_long_classes(pa, ctx, lo, hi, n, m, prec, monkeypatch):
         assert int(y[-1]) >> (m % 64) == 0 if m % 64 else True
     s = pa.pa_last_stats(ctx)
     assert s["tiles"] == plan["chunks"] * plan["windows"]
+    if prec == "fp32":
+        assert s["max_residual"] <= s["bound"], s   # the error model holds on random inputs
     print(prec, lo, n, m, "residual", s["max_residual"], flush=True)
 
 

@@ -126,6 +126,40 @@ def test_error_model_monotone(pa):
     assert pa.pa_error_model(0x00F0, 20, 5) < 0
 
 
+def _fp32_packed_conv_error(rng, logL, Bi, centre_key):
+    """Max error over the kept window of the packed two-for-one FP32 FFT
+    convolution of a 0/1 chunk (or the same chunk minus 1/2) with a +-1 seed,
+    computed with scipy's single-precision FFT."""
+    import scipy.fft as sf
+    L = 1 << logL
+    Bo = L - Bi + 1
+    x = np.zeros(L)
+    x[:Bi] = rng.integers(0, 2, Bi)
+    if centre_key:
+        x[:Bi] -= 0.5
+    w = (1.0 - 2.0 * rng.integers(0, 2, L)).astype(np.float64)
+    exact = np.fft.ifft(np.fft.fft(x) * np.fft.fft(w)).real
+    Z = sf.fft((x + 1j * w).astype(np.complex64))
+    Zr = np.conj(np.roll(Z[::-1], 1))
+    P = ((Z + Zr) / 2 * ((Z - Zr) / np.complex64(2j))).astype(np.complex64)
+    y = sf.ifft(P).real
+    return float(np.abs(y - exact)[Bi - 1:Bi - 1 + Bo].max())
+
+
+def test_error_model_covers_fp32_packed_convolution(pa):
+    """The error model bounds the error of an FP32 packed convolution (here
+    scipy's FFT, not the kernels), and its low-frequency term is real: the same
+    convolution with the key's mean removed is several times more accurate."""
+    rng = np.random.default_rng(7)
+    f = pa.PA_PREC_FP32_SEG
+    for logL, Bi in [(18, 1 << 17), (18, 3 << 15), (20, 1 << 19)]:
+        err = _fp32_packed_conv_error(rng, logL, Bi, False)
+        assert err <= pa.pa_error_model(f, logL, Bi), (logL, Bi, err)
+    e01 = _fp32_packed_conv_error(np.random.default_rng(8), 20, 1 << 19, False)
+    e_centred = _fp32_packed_conv_error(np.random.default_rng(8), 20, 1 << 19, True)
+    assert e_centred * 1.5 < e01, (e01, e_centred)
+
+
 def test_plan_query_rejects_bad_input(pa):
     with pytest.raises(pa.PAError):
         pa.pa_plan_query(0, 5, 0)
