@@ -124,7 +124,7 @@ def run_batch(pa, ctx, torch, jobs, flags, steps, warmup):
     return dict(elapsed=el, stats=pa.pa_last_stats(ctx), outs=outs)
 
 
-def run_serving(pa, torch, count: int, load: float = 0.7, budget_gib: int = 8):
+def run_serving(pa, chk_ctx, torch, count: int, load: float = 0.7, budget_gib: int = 8):
     """Serving workload: `count` requests, n log-uniform in [1e5, 1e8], m/n
     uniform in [0.02, 0.5], seeds = 8 resident 1.5e8-bit strings, Poisson
     arrivals.  Request keys are prefixes of 8 resident random 1e8-bit
@@ -132,8 +132,9 @@ def run_serving(pa, torch, count: int, load: float = 0.7, budget_gib: int = 8):
     capacity measured on a back-to-back burst of the same requests, on a
     context of its own with an HBM budget of `budget_gib` GiB.  Beside the
     main leg: a sweep of the load (0.5 and 0.9, 500 requests each) and the
-    same 500 requests at 0.7 under a 1 GiB budget, where admission binds."""
-    import oracle
+    same 500 requests at 0.7 under a 1 GiB budget, where admission binds.
+    Exactness: 256 outputs of each of 16 requests recomputed by
+    pa_hash_select (the direct GF(2) product, no transform) on chk_ctx."""
     import synth
     seeds, reqs = synth.serving_stream(count)
     rng = np.random.default_rng(5)
@@ -207,19 +208,80 @@ def run_serving(pa, torch, count: int, load: float = 0.7, budget_gib: int = 8):
         log(f"[bench] serving tight budget: {tight}")
     finally:
         pa.pa_destroy(tctx)
-    # exactness spot check: 64 output bits of 8 requests, word-parallel oracle
-    chk = np.random.default_rng(6).choice(len(reqs), size=min(8, len(reqs)), replace=False)
+    # exactness spot check on the device by the direct path
+    chk = np.random.default_rng(6).choice(len(reqs), size=min(16, len(reqs)), replace=False)
     exact = True
     for k in chk:
         r = reqs[int(k)]
-        idx = np.random.default_rng(int(k)).integers(0, r["m"], 64)
-        ref = oracle.hash_select(seeds[r["seed_id"]], r["n"], r["m"], keys[int(k) % 8], idx)
+        idx = np.random.default_rng(int(k)).integers(0, r["m"], 256)
+        st, ref = pa.pa_hash_select(chk_ctx, dseeds[r["seed_id"]], r["n"], r["m"], dkeys[int(k) % 8], idx)
+        assert st == pa.PA_OK, pa.pa_strerror(st)
         got = synth.bits_to_array(outs[int(k)].cpu().numpy().view(np.uint64), r["m"])[idx]
         exact = exact and bool(np.array_equal(ref, got))
     main["spot_check_exact"] = exact
+    main["spot_check"] = "256 outputs of 16 requests recomputed by pa_hash_select (direct GF(2) product)"
     main["sweep"] = sweep
     main["tight_budget"] = tight
     return main
+
+
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+
+
+def run_direct_leg(pa, ctx, torch, steps, warmup, m: int = 1000):
+    """The c3 key (n = 12,345,679) with a short output (m = 1000): the direct
+    GF(2) path against the FP32 FFT path on the same job.  Both are product
+    paths; their outputs must agree bit for bit.  The direct kernel does two
+    VALU operations per output and 32-bit key word; its ALU roofline is the
+    vector rate of the chip."""
+    import synth
+    rng = np.random.default_rng(2)
+    prob = synth.random_problem(rng, 12_345_679, m)
+    rd = run_single(pa, ctx, torch, prob, pa.PA_PREC_DIRECT, steps, warmup)
+    rf = run_single(pa, ctx, torch, prob, pa.PA_PREC_FP32_SEG, steps, warmup)
+    key_words = -(-(-(-prob.n // 32)) // 4) * 4          # ceil(n / 32) rounded up to 4
+    steps_word = (-(-m // 256) * 256) * key_words       # outputs in blocks of 256
+    kms = rd["kernel_ms"][0]
+    ops = 2.0 * steps_word / (kms * 1e-3)
+    return {"n": prob.n, "m": m,
+            "direct_gbps": round(prob.n * steps / rd["elapsed"] / 1e9, 3),
+            "direct_ms_per_call": round(rd["elapsed"] / steps * 1e3, 4),
+            "fft_fp32_gbps": round(prob.n * steps / rf["elapsed"] / 1e9, 3),
+            "fft_ms_per_call": round(rf["elapsed"] / steps * 1e3, 4),
+            "outputs_agree": bool(np.array_equal(rd["out"], rf["out"])),
+            "roofline": {"bound": "alu", "kernel": "k_direct", "achieved": round(ops / 1e12, 2),
+                         "peak": round(VALU_LANE_OPS / 1e12, 2), "unit": "T lane-ops/s",
+                         "frac": round(ops / VALU_LANE_OPS, 4), "kernel_ms": round(kms, 5)}}
+
+
+# Table 1 of the paper (NVIDIA TITAN Xp, FP32 FFT, m = 0.1 n): Gbps per input length
+PAPER_TABLE1 = {4: 1.25, 8: 1.33, 16: 1.37, 32: 1.38, 64: 1.38, 128: 1.35}
+
+
+def run_table1(pa, ctx, torch, reps: int = 5):
+    """The paper's Table 1 shapes on this GPU: n = 4..128 Mbit (10^6 bits),
+    m = 0.1 n, random bits, PA_PREC_AUTO.  Each result is checked on 256
+    random outputs by pa_hash_select (the direct product)."""
+    import synth
+    out = []
+    rng = np.random.default_rng(7)
+    for mb, paper in PAPER_TABLE1.items():
+        n = mb * 1_000_000
+        m = n // 10
+        prob = synth.random_problem(rng, n, m)
+        r = run_single(pa, ctx, torch, prob, pa.PA_PREC_AUTO, reps, 2)
+        idx = rng.integers(0, m, 256)
+        s = torch.from_numpy(prob.seed.view(np.int64).copy()).to("cuda:0")
+        k = torch.from_numpy(prob.key.view(np.int64).copy()).to("cuda:0")
+        st, ref = pa.pa_hash_select(ctx, s, n, m, k, idx)
+        assert st == pa.PA_OK, pa.pa_strerror(st)
+        ok = bool(np.array_equal(ref, synth.bits_to_array(r["out"], m)[idx]))
+        row = {"mbit": mb, "n": n, "m": m, "gbps": round(n * reps / r["elapsed"] / 1e9, 2),
+               "ms_per_call": round(r["elapsed"] / reps * 1e3, 3), "log2_len": r["stats"]["log2_len"],
+               "tiles": r["stats"]["tiles"], "spot_check_exact": ok, "paper_titan_xp_gbps": paper}
+        log(f"[bench] table-1 shape: {row}")
+        out.append(row)
+    return out
 
 
 def cpu_baseline(prob, target_s: float = 12.0):
@@ -252,6 +314,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-job batch measurement")
     ap.add_argument("--serve", type=int, default=2000, help="requests in the serving leg (0: skip)")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None, help="run one path only (profiling)")
+    ap.add_argument("--no-direct", action="store_true", help="skip the direct-path (short output) leg")
+    ap.add_argument("--no-table1", action="store_true", help="skip the 4-128 Mbit sweep")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 512 MiB device copy (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -298,10 +362,18 @@ def main():
         batch["gbps"] = sum(p.n for p in jobs) * bsteps / batch["elapsed"] / 1e9
         log(f"[bench] c4: {batch['gbps']:.2f} Gbps bit-exact={bexact}")
 
+    direct = None
+    if not args.only and not args.no_direct:
+        direct = run_direct_leg(pa, ctx, torch, args.steps, args.warmup)
+        log(f"[bench] direct leg: {direct}")
+    table1 = None
+    if not args.only and not args.no_table1:
+        table1 = run_table1(pa, ctx, torch)
+
     serving = None
     if args.serve and not args.only:
         log(f"[bench] serving leg, {args.serve} requests")
-        serving = run_serving(pa, torch, args.serve)
+        serving = run_serving(pa, ctx, torch, args.serve)
         log(f"[bench] serving: {serving}")
 
     if args.calib_copy:
@@ -378,6 +450,12 @@ def main():
         line["batch_c4"] = {"jobs": 64, "gbps": round(batch["gbps"], 3), "tiles": batch["stats"]["tiles"],
                             "log2_len": batch["stats"]["log2_len"], "bit_exact": bool(batch["bit_exact"]),
                             "fallback_tiles": batch["stats"]["fallback_tiles"]}
+    if batch is not None:
+        line["batch_c4"]["direct_jobs"] = batch["stats"]["direct_jobs"]
+    if direct is not None:
+        line["direct_short_output"] = direct
+    if table1 is not None:
+        line["table1_sweep"] = table1
     if serving is not None:
         line["serving_c5"] = serving
     if not args.no_cpu:

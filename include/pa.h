@@ -51,10 +51,14 @@ typedef enum {
 
 /* ---- flags ---------------------------------------------------------------- */
 #define PA_DEVICE_PTRS    0x0001u  /* seed/key/out are device pointers                 */
-#define PA_PREC_AUTO      0x0000u  /* fastest certified plan (FP32 tiles + FP64 fallback) */
+#define PA_PREC_AUTO      0x0000u  /* fastest exact plan: the direct product where it is
+                                      modeled cheaper (short outputs), else FP32 tiles
+                                      with FP64 fallback                                */
 #define PA_PREC_FP32_SEG  0x0010u  /* FP32 FFT tiles sized by the rounding bound        */
 #define PA_PREC_FP64      0x0020u  /* FP64 FFT, one tile where it fits ("plain" path)   */
 #define PA_PREC_NTT       0x0030u  /* exact number-theoretic transform mod 15*2^27+1    */
+#define PA_PREC_DIRECT    0x0040u  /* exact word-parallel GF(2) product, no transform:
+                                      ceil(n/32) word steps per output (short outputs) */
 #define PA_PREC_MASK      0x00F0u
 #define PA_NO_FALLBACK    0x0100u  /* report PA_EPRECISION instead of re-running FP64   */
 #define PA_ASYNC          0x0200u  /* with PA_DEVICE_PTRS and an exact or a-priori
@@ -102,6 +106,17 @@ typedef struct {
 pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs, uint64_t count, uint32_t flags,
                         pa_status* per_job);
 
+/* Output bits y[idx[k]], k < count, computed exactly by the direct GF(2)
+ * product (section 2.1, Eq. 1: each bit is the parity of the seed window at
+ * idx[k] AND-ed with the reversed key), which shares nothing with the FFT
+ * path: an on-device check of any chosen outputs.  seed (n+m-1 bits) and key
+ * (n bits) as for pa_hash (PA_DEVICE_PTRS); idx (count indices < m) and bits
+ * (count bytes, each 0 or 1, written) are host arrays.  count <= 2^20; count
+ * == 0 is a no-op.  Synchronous.  PA_EINVAL for an index >= m, NULL pointers
+ * or count > 2^20. */
+pa_status pa_hash_select(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, const uint64_t* key,
+                         const uint64_t* idx, uint64_t count, uint8_t* bits, uint32_t flags);
+
 /* ---- serving (continuous batching) --------------------------------------- */
 
 /* Copy a seed of nbits bits (device pointer if PA_DEVICE_PTRS in flags, else
@@ -143,8 +158,11 @@ typedef struct {
     double bound;             /* predicted max error of the plan              */
     double ms_pass[4];        /* PA_TIMING: summed kernel ms of pass 1, 2, 3; [3] is 0
                                  (key chunks are XOR-merged inside pass 3)  */
-    uint64_t model_bytes;     /* algorithmic HBM bytes of the FFT passes      */
+    uint64_t model_bytes;     /* algorithmic HBM bytes of the FFT passes (direct
+                                 path: seed, key and output once)             */
     uint64_t launches;        /* kernel launches                              */
+    uint64_t direct_jobs;     /* jobs that ran on the direct path (prec is
+                                 PA_PREC_DIRECT when all of them did)         */
 } pa_stats;
 
 /* Statistics of the last pa_hash / pa_hash_batch on this context. */
@@ -189,6 +207,10 @@ typedef struct {
     uint64_t windows;     /* ceil(m / Bo) */
     double bound;         /* predicted max error (probabilistic model)  */
     double cost;          /* model cost used to choose the plan          */
+    double direct_cost;   /* model cost of the direct path for (n, m)    */
+    uint32_t direct;      /* 1: the flags run (n, m) on the direct path; the
+                             fields above still describe the FFT plan   */
+    uint32_t reserved;
 } pa_plan;
 
 /* The plan pa_hash would use for (n, m) under the precision bits of flags,

@@ -225,6 +225,7 @@ void Lane::release(Ctx* c) {
     meta.release(c);
     jobs_dev.release(c);
     io.release(c);
+    aux.release(c);
     meta_host.release();
     jobs_host.release();
     timer.destroy();
@@ -433,9 +434,22 @@ pa_status Lane::finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_s
     return result;
 }
 
+pa_status Lane::direct(Ctx* c, const uint64_t* seed, const uint64_t* key, uint64_t n, uint64_t m, uint64_t* out,
+                       bool timing, pa_stats* stats) {
+    pa_status st = aux.ensure(c, direct_key_words(n) * 4);
+    if (st != PA_OK) return st;
+    hipEvent_t a = timing ? timer.mark(stream) : nullptr;
+    if (launch_direct(seed, key, n, m, out, (uint32_t*)aux.ptr, stream, &stats->launches)) return PA_EDEVICE;
+    if (timing) timer.spans.push_back({0, {a, timer.mark(stream)}});
+    stats->direct_jobs += 1;
+    stats->model_bytes += (words_of(n + m - 1) + words_of(n) + words_of(m)) * 8;
+    return PA_OK;
+}
+
 int policy_of(uint32_t flags) {
     switch (flags & PA_PREC_MASK) {
         case PA_PREC_AUTO: return PREC_FP32;
+        case PA_PREC_DIRECT: return PREC_FP32;   // the FFT plan describes the job
         case PA_PREC_FP32_SEG: return PREC_FP32;
         case PA_PREC_FP64: return PREC_FP64;
         case PA_PREC_NTT: return PREC_NTT;
@@ -541,14 +555,33 @@ pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, con
         dkey = base + sw;
         dout = base + sw + kw;
     }
-    std::vector<JobDesc> jobs(1);
-    fill_job(&jobs[0], dseed, dkey, dout, n, m, plan);
-    // Only an a-priori certified plan may skip the certificate read-back;
-    // kernel timing needs the launch to finish.
     const bool timing = flags & PA_TIMING;
-    const bool async = dev && (flags & PA_ASYNC) && plan.prec != PREC_FP32 && !timing;
-    pa_status s = ln.launch(c, plan.prec, plan.logL, jobs, timing, !async, &st);
-    if (s == PA_OK && !async) s = ln.finish(c, flags, &st, nullptr);
+    pa_status s = PA_OK;
+    CostModel cm;
+    {
+        std::lock_guard<std::mutex> pk(c->plan_mu);
+        cm = c->cost;
+    }
+    if (choose_direct(flags, n, m, cm, plan)) {
+        // exact: no certificate, so PA_ASYNC may return once enqueued
+        st = pa_stats{};
+        st.prec = PA_PREC_DIRECT;
+        st.chunk_bits = n;
+        st.window_bits = m;
+        if (timing) ln.timer.reset();
+        s = ln.direct(c, dseed, dkey, n, m, dout, timing, &st);
+        const bool async = dev && (flags & PA_ASYNC) && !timing;
+        if (s == PA_OK && !async && hipStreamSynchronize(ln.stream) != hipSuccess) s = PA_EDEVICE;
+        if (s == PA_OK && timing) ln.timer.collect(st.ms_pass);
+    } else {
+        std::vector<JobDesc> jobs(1);
+        fill_job(&jobs[0], dseed, dkey, dout, n, m, plan);
+        // Only an a-priori certified plan may skip the certificate read-back;
+        // kernel timing needs the launch to finish.
+        const bool async = dev && (flags & PA_ASYNC) && plan.prec != PREC_FP32 && !timing;
+        s = ln.launch(c, plan.prec, plan.logL, jobs, timing, !async, &st);
+        if (s == PA_OK && !async) s = ln.finish(c, flags, &st, nullptr);
+    }
     if (s == PA_OK && !dev) {
         if (hipMemcpyAsync(out, dout, ow * 8, hipMemcpyDeviceToHost, ln.stream) != hipSuccess ||
             hipStreamSynchronize(ln.stream) != hipSuccess)
@@ -603,8 +636,33 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
     std::lock_guard<std::mutex> lk(c->mu);
     if (hipSetDevice(c->device) != hipSuccess) return PA_EDEVICE;
     Lane& ln = c->main;
+    CostModel cm;
+    {
+        std::lock_guard<std::mutex> pk(c->plan_mu);
+        cm = c->cost;
+    }
+    // jobs on the direct path, and the FFT jobs (planned in length-class groups)
+    std::vector<char> is_direct(count, 0);
+    std::vector<uint64_t> fns, fms;
+    std::vector<size_t> fidx;
+    std::vector<TilePlan> fplans;
+    for (uint64_t i = 0; i < count; ++i) {
+        TilePlan p;
+        if (!c->plan_cached(ns[i], ms[i], policy, &p)) return PA_EINVAL;
+        is_direct[i] = choose_direct(flags, ns[i], ms[i], cm, p);
+        if (!is_direct[i]) {
+            fidx.push_back(i);
+            fns.push_back(ns[i]);
+            fms.push_back(ms[i]);
+            fplans.push_back(p);
+        }
+    }
     std::vector<BatchGroup> groups;
-    if (!plan_batch_groups(ns, ms, policy, c->cost, &groups)) return PA_EINVAL;
+    if (!fidx.empty()) {
+        if (!plan_batch_groups(fns, fms, policy, cm, &groups, &fplans)) return PA_EINVAL;
+        for (BatchGroup& g : groups)
+            for (size_t& q : g.jobs) q = fidx[q];
+    }
     std::vector<const TilePlan*> plan_of(count, nullptr);
     pa_stats st{};
     for (const BatchGroup& g : groups)   // ascending classes: the stats name the largest
@@ -642,7 +700,15 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
             out_off[i] = off + sw + kw;
             off += sw + kw + ow;
         }
-        fill_job(&all[i], dseed, dkey, dout, j.n, j.m, *plan_of[i]);
+        if (is_direct[i]) {   // pointers only
+            all[i].seed = dseed;
+            all[i].key = dkey;
+            all[i].out = dout;
+            all[i].n = j.n;
+            all[i].m = j.m;
+        } else {
+            fill_job(&all[i], dseed, dkey, dout, j.n, j.m, *plan_of[i]);
+        }
     }
     // One pipeline launch per length class.  The groups run concurrently on
     // the context's stream and on side streams (forked from it), largest
@@ -660,6 +726,18 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
         (void)hipEventDestroy(fork);
         if (!ok) return PA_EDEVICE;
     }
+    // direct jobs on the context's stream, beside the side streams' groups
+    pa_stats dst{};
+    const size_t ndirect = count - fidx.size();
+    for (uint64_t i = 0; i < count && s == PA_OK; ++i) {
+        if (!is_direct[i]) continue;
+        const pa_status ds = ln.direct(c, all[i].seed, all[i].key, all[i].n, all[i].m, all[i].out, false, &dst);
+        if (ds != PA_OK) {
+            status[i] = ds;
+            s = ds;
+        }
+    }
+    bool stop = s != PA_OK;
     std::vector<size_t> order(groups.size());
     for (size_t g = 0; g < order.size(); ++g) order[g] = g;
     std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return groups[a].cost > groups[b].cost; });
@@ -667,7 +745,6 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
     std::vector<pa_stats> lst(lanes.size(), pa_stats{});
     std::deque<size_t> queue(order.begin(), order.end());
     std::deque<size_t> fifo;                              // lanes in launch order
-    bool stop = false;
     while (true) {
         for (size_t k = 0; k < lanes.size() && !stop && !queue.empty(); ++k) {
             if (on_lane[k] >= 0) continue;
@@ -698,7 +775,12 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
         if (!per_tile) stop = true;
         if (stop) queue.clear();
     }
+    if (ndirect && hipStreamSynchronize(ln.stream) != hipSuccess && s == PA_OK) s = PA_EDEVICE;
+    lst.push_back(dst);
+    st.direct_jobs = dst.direct_jobs;
+    if (fidx.empty()) st.prec = PA_PREC_DIRECT;
     for (const pa_stats& x : lst) {
+        st.model_bytes += x.model_bytes;
         st.tiles += x.tiles;
         st.fallback_tiles += x.fallback_tiles;
         st.launches += x.launches;
@@ -750,10 +832,59 @@ pa_status pa_plan_query(uint64_t n, uint64_t m, uint32_t flags, pa_plan* out) {
     out->windows = p.nouts;
     out->bound = p.bound;
     out->cost = p.cost;
+    out->direct_cost = direct_cost(n, m, cm);
+    out->direct = choose_direct(flags, n, m, cm, p) ? 1u : 0u;
+    out->reserved = 0;
+    return PA_OK;
+}
+
+pa_status pa_hash_select(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, const uint64_t* key,
+                         const uint64_t* idx, uint64_t count, uint8_t* bits, uint32_t flags) {
+    if (!ctx || !seed || !key || n == 0 || m == 0 || n > (1ull << 40) || m > (1ull << 40)) return PA_EINVAL;
+    if (count == 0) return PA_OK;
+    if (!idx || !bits || count > (1ull << 20)) return PA_EINVAL;
+    for (uint64_t k = 0; k < count; ++k)
+        if (idx[k] >= m) return PA_EINVAL;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return PA_EDEVICE;
+    Lane& ln = c->main;
+    const uint64_t *dseed = seed, *dkey = key;
+    if (!(flags & PA_DEVICE_PTRS)) {
+        const uint64_t sw = words_of(n + m - 1), kw = words_of(n);
+        pa_status s = ln.io.ensure(c, (sw + kw) * 8);
+        if (s != PA_OK) return s;
+        uint64_t* base = (uint64_t*)ln.io.ptr;
+        if (hipMemcpyAsync(base, seed, sw * 8, hipMemcpyHostToDevice, ln.stream) != hipSuccess ||
+            hipMemcpyAsync(base + sw, key, kw * 8, hipMemcpyHostToDevice, ln.stream) != hipSuccess)
+            return PA_EDEVICE;
+        dseed = base;
+        dkey = base + sw;
+    }
+    // scratch: reversed key | indices | result bits (256-byte aligned sections)
+    auto up = [](uint64_t b) { return (b + 255) & ~uint64_t(255); };
+    const uint64_t kr_bytes = up(direct_key_words(n) * 4), idx_bytes = up(count * 8), res_words = words_of(count);
+    pa_status s = ln.aux.ensure(c, kr_bytes + idx_bytes + res_words * 8);
+    if (s == PA_OK) s = ln.jobs_host.ensure(idx_bytes + res_words * 8);
+    if (s != PA_OK) return s;
+    uint8_t* dbase = (uint8_t*)ln.aux.ptr;
+    uint64_t* didx = (uint64_t*)(dbase + kr_bytes);
+    uint64_t* dres = (uint64_t*)(dbase + kr_bytes + idx_bytes);
+    uint64_t* hidx = (uint64_t*)ln.jobs_host.ptr;
+    uint64_t* hres = (uint64_t*)((uint8_t*)ln.jobs_host.ptr + idx_bytes);
+    memcpy(hidx, idx, count * 8);
+    if (hipMemcpyAsync(didx, hidx, count * 8, hipMemcpyHostToDevice, ln.stream) != hipSuccess) return PA_EDEVICE;
+    if (launch_direct_select(dseed, dkey, n, m, didx, (uint32_t)count, dres, (uint32_t*)dbase, ln.stream))
+        return PA_EDEVICE;
+    if (hipMemcpyAsync(hres, dres, res_words * 8, hipMemcpyDeviceToHost, ln.stream) != hipSuccess ||
+        hipStreamSynchronize(ln.stream) != hipSuccess)
+        return PA_EDEVICE;
+    for (uint64_t k = 0; k < count; ++k) bits[k] = (uint8_t)((hres[k >> 6] >> (k & 63)) & 1u);
     return PA_OK;
 }
 
 double pa_error_model(uint32_t prec, uint32_t log2_len, uint64_t chunk_bits) {
+    if ((prec & PA_PREC_MASK) == PA_PREC_DIRECT) return 0.0;   // exact
     const int p = policy_of(prec);
     if (p < 0) return -1.0;
     return error_bound(p, (int)log2_len, chunk_bits);

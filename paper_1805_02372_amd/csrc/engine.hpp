@@ -58,6 +58,7 @@ struct Lane {
     bool own_stream = false;
     uint64_t cap = 0;     // workspace cap in bytes (0: the context budget)
     DevBuf ws, part, meta, jobs_dev, io;
+    DevBuf aux;           // direct path: reversed key, selected indices and bits
     HostBuf meta_host, jobs_host;
     PassTimer timer;
 
@@ -78,6 +79,10 @@ struct Lane {
     // tiles (whole jobs when they accumulate chunks) in FP64.  Synchronous on
     // this lane's stream.
     pa_status finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_status>* per_job);
+    // Enqueue the direct GF(2) product of one job (device pointers); out is
+    // written completely.  Asynchronous on this lane's stream.
+    pa_status direct(Ctx* c, const uint64_t* seed, const uint64_t* key, uint64_t n, uint64_t m, uint64_t* out,
+                     bool timing, pa_stats* stats);
 };
 
 // One serving request.

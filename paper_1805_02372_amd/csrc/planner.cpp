@@ -5,6 +5,8 @@
 // one FFT length class.
 #include "planner.hpp"
 
+#include "pa.h"
+
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -94,22 +96,31 @@ static double unit_roundoff(int prec) {
 // into the separated W_k, and the product picks up about u |X_k|^2 there.  The
 // inverse transform spreads these few bins over every output as a smooth
 // wave of rms u sqrt(sum_k 2 (D_k / 2)^4) / L; the sum converges like k^-4 and
-// 64 terms hold it.  The maximum over a tile is about 2-4 times the rms.
+// 16 terms hold it (the rest is below 10^-4 of it).  The maximum over a tile
+// is about 2-4 times the rms.
 static double box_leak_rms(int prec, int logL, uint64_t Bi) {
     const double L = std::ldexp(1.0, logL);
     const uint64_t twoL = 2ull << logL;
-    double s4 = 0;
-    for (uint64_t k = 1; k <= 64 && (double)k < L / 2; ++k) {
-        const uint64_t r = (Bi % twoL) * k % twoL;   // pi Bi k / L reduced mod 2 pi
-        const double d = std::fabs(std::sin(M_PI * (double)r / L) / std::sin(M_PI * (double)k / L)) / 2;
+    // sin(pi Bi k / L) and sin(pi k / L) for k = 1, 2, ... by rotation
+    const double a = M_PI * (double)(Bi % twoL) / L, b = M_PI / L;
+    const double sa = std::sin(a), ca = std::cos(a), sb = std::sin(b), cb = std::cos(b);
+    double sak = sa, cak = ca, sbk = sb, cbk = cb, s4 = 0;
+    for (uint64_t k = 1; k <= 16 && (double)k < L / 2; ++k) {
+        const double d = std::fabs(sak / sbk) / 2;
         s4 += 2 * d * d * d * d;
+        const double s1 = sak * ca + cak * sa, c1 = cak * ca - sak * sa;
+        const double s2 = sbk * cb + cbk * sb, c2 = cbk * cb - sbk * sb;
+        sak = s1, cak = c1, sbk = s2, cbk = c2;
     }
     return unit_roundoff(prec) * std::sqrt(s4) / L;
 }
 
 double error_bound(int prec, int logL, uint64_t Bi) {
     if (prec == PREC_NTT) return 0.0;
-    return 6.0 * g_kappa * unit_roundoff(prec) * std::sqrt((double)logL * (double)Bi) +
+    // the noise term: the packed transform carries the seed's norm sqrt(L)
+    // beside the chunk's sqrt(Bi), so even a one-bit chunk sees u sqrt(L log L)
+    const double L = std::ldexp(1.0, logL);
+    return 6.0 * g_kappa * unit_roundoff(prec) * std::sqrt((double)logL * ((double)Bi + L)) +
            5.0 * box_leak_rms(prec, logL, Bi);
 }
 
@@ -123,6 +134,9 @@ double rigorous_bound(int prec, int logL, uint64_t Bi, uint64_t Bo) {
 
 CostModel::CostModel() {
     launch_s = 12e-6;
+    // two VALU operations per output and key word at half the vector rate
+    // (256 CUs x 64 lanes x 2.4 GHz)
+    direct_s = 1.0e-13;
     for (int p = 0; p < 3; ++p)
         for (int k = 0; k < 32; ++k) {
             const double L = std::ldexp(1.0, k);
@@ -137,6 +151,17 @@ CostModel::CostModel() {
 double CostModel::tile(int prec, int logL) const { return tile_s[prec_index(prec)][logL]; }
 void CostModel::set(int prec, int logL, double s) { tile_s[prec_index(prec)][logL] = s; }
 
+double direct_cost(uint64_t n, uint64_t m, const CostModel& cm) {
+    const double outs = (double)(ceil_div(m, 256) * 256), words = (double)(ceil_div(ceil_div(n, 32), 4) * 4);
+    return cm.launch_s + cm.direct_s * outs * words;
+}
+
+bool choose_direct(uint32_t flags, uint64_t n, uint64_t m, const CostModel& cm, const TilePlan& fft) {
+    const uint32_t p = flags & PA_PREC_MASK;
+    if (p == PA_PREC_DIRECT) return true;
+    return p == PA_PREC_AUTO && direct_cost(n, m, cm) < fft.cost;
+}
+
 bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& cm, TilePlan* out) {
     ClassGeom g;
     if (n == 0 || m == 0 || !class_geometry(prec, logL, &g)) return false;
@@ -145,7 +170,7 @@ bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& 
     uint64_t bi_cap = n;
     if (prec != PREC_NTT) {
         const double per = 6.0 * g_kappa * unit_roundoff(prec) * std::sqrt((double)logL);
-        const double cap = std::floor((kPlanErrorLimit / per) * (kPlanErrorLimit / per));
+        const double cap = std::floor((kPlanErrorLimit / per) * (kPlanErrorLimit / per) - (double)L);
         if (cap < (double)bi_cap) bi_cap = (uint64_t)std::max(0.0, cap);
     }
     TilePlan best;
@@ -153,7 +178,8 @@ bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& 
     const uint64_t max_outs = std::min<uint64_t>(ceil_div(m, 64), 1u << 14);
     uint64_t last_bo = 0;
     const uint64_t min_chunks = ceil_div(n, std::min<uint64_t>(L, bi_cap == 0 ? 1 : bi_cap));
-    for (uint64_t w = 1; w <= std::max<uint64_t>(1, max_outs); ++w) {
+    // fewer than ceil(m / L) windows cannot fit a window in L
+    for (uint64_t w = std::max<uint64_t>(1, ceil_div(m, L)); w <= std::max<uint64_t>(1, max_outs); ++w) {
         // every later candidate has >= w windows and >= min_chunks chunks
         if (found && w * min_chunks >= best.tiles()) break;
         uint64_t Bo = (w == 1) ? m : round_up64(ceil_div(m, w));
@@ -188,14 +214,15 @@ bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& 
 bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan* out) {
     if (n == 0 || m == 0) return false;
     const int prec = policy;
+    const int lo = min_logL(prec), hi = max_logL(prec);
     if (prec == PREC_FP64 || prec == PREC_NTT) {
         // one tile at the smallest class that holds the whole product
-        for (int k = min_logL(prec); k <= max_logL(prec); ++k)
+        for (int k = lo; k <= hi; ++k)
             if (n + m - 1 <= (1ull << k)) return plan_at_class(n, m, prec, k, cm, out);
     }
     bool found = false;
     TilePlan best;
-    for (int k = min_logL(prec); k <= max_logL(prec); ++k) {
+    for (int k = lo; k <= hi; ++k) {
         TilePlan p;
         if (!plan_at_class(n, m, prec, k, cm, &p)) continue;
         if (!found || p.cost < best.cost) {
@@ -208,12 +235,26 @@ bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan*
 }
 
 bool plan_batch_groups(const std::vector<uint64_t>& ns, const std::vector<uint64_t>& ms, int policy,
-                       const CostModel& cm, std::vector<BatchGroup>* groups) {
-    if (ns.empty() || ns.size() != ms.size()) return false;
+                       const CostModel& cm, std::vector<BatchGroup>* groups, const std::vector<TilePlan>* own) {
+    if (ns.empty() || ns.size() != ms.size() || (own && own->size() != ns.size())) return false;
+    // plans of job i at class k, computed once: memo[i * NK + k - 12], state 0
+    // unknown, 1 found, -1 none
+    constexpr int NK = 13;
+    std::vector<TilePlan> memo(ns.size() * NK);
+    std::vector<signed char> known(ns.size() * NK, 0);
+    auto at_class = [&](size_t i, int k, TilePlan* p) {
+        const size_t x = i * NK + (size_t)(k - 12);
+        if (k < 12 || k >= 12 + NK) return false;
+        if (!known[x]) known[x] = plan_at_class(ns[i], ms[i], policy, k, cm, &memo[x]) ? 1 : -1;
+        if (known[x] < 0) return false;
+        *p = memo[x];
+        return true;
+    };
     std::map<int, BatchGroup> by_class;
     for (size_t i = 0; i < ns.size(); ++i) {
         TilePlan p;
-        if (!plan_job(ns[i], ms[i], policy, cm, &p)) return false;
+        if (own) p = (*own)[i];
+        else if (!plan_job(ns[i], ms[i], policy, cm, &p)) return false;
         BatchGroup& g = by_class[p.logL];
         g.logL = p.logL;
         g.jobs.push_back(i);
@@ -238,7 +279,7 @@ bool plan_batch_groups(const std::vector<uint64_t>& ns, const std::vector<uint64
                 bool ok = true;
                 for (size_t q = 0; q < gs[g].jobs.size() && ok; ++q) {
                     const size_t i = gs[g].jobs[q];
-                    ok = plan_at_class(ns[i], ms[i], policy, gs[h].logL, cm, &moved[q]);
+                    ok = at_class(i, gs[h].logL, &moved[q]);
                     c += moved[q].cost - cm.launch_s;
                 }
                 if (!ok) continue;

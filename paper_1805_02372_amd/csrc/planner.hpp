@@ -7,7 +7,7 @@
 
 namespace pa {
 
-enum Prec { PREC_FP32 = 32, PREC_FP64 = 64, PREC_NTT = 1 };
+enum Prec { PREC_FP32 = 32, PREC_FP64 = 64, PREC_NTT = 1, PREC_DIRECT = 2 };
 
 struct ClassGeom {
     int prec, logL, n1, n2, b1, b3, r;
@@ -23,6 +23,7 @@ int max_logL(int prec);
 struct CostModel {
     double tile_s[3][32];   // [0] FP32, [1] FP64, [2] NTT; index logL
     double launch_s;        // fixed cost of one pipeline launch
+    double direct_s;        // direct GF(2) path: seconds per output per 32-bit key word
     CostModel();
     double tile(int prec, int logL) const;
     void set(int prec, int logL, double s);
@@ -38,7 +39,7 @@ struct TilePlan {
 // Error model of one floating-point tile, a predicted maximum of the output
 // error for an FFT convolution of a +-1 sequence with a 0/1 chunk of Bi bits at
 // length 2^logL: 6 sigma of the random rounding noise, sigma = kappa u
-// sqrt(logL Bi), plus 5 times the rms of the low-frequency error that the
+// sqrt(logL (Bi + L)), plus 5 times the rms of the low-frequency error that the
 // chunk's zero padding causes (about 0.036 u L once Bi > L/3; the larger term
 // from 2^22 on in FP32).
 double error_bound(int prec, int logL, uint64_t Bi);
@@ -51,6 +52,14 @@ double error_kappa();
 // The admissible error for a floating-point plan before the a-posteriori
 // certificate (half the rounding margin of 0.5).
 constexpr double kPlanErrorLimit = 0.25;
+
+// Modeled time of the direct GF(2) path for one job: outputs are processed in
+// blocks of 256, each against ceil(n/32) key words (rounded up to 4).
+double direct_cost(uint64_t n, uint64_t m, const CostModel& cm);
+// Whether the precision bits of `flags` put job (n, m) on the direct path:
+// always for PA_PREC_DIRECT; for PA_PREC_AUTO when the direct path is modeled
+// cheaper than the FFT plan `fft`.
+bool choose_direct(uint32_t flags, uint64_t n, uint64_t m, const CostModel& cm, const TilePlan& fft);
 
 // Best (Bi, Bo) for job (n, m) at a fixed class; false if impossible.
 bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& cm, TilePlan* out);
@@ -71,9 +80,11 @@ struct BatchGroup {
 // Batch plan with one launch per length class: every job starts in its own
 // cheapest class, then a group is folded into another group's class while that
 // lowers the summed cost (tiles plus one launch per group).  Groups come out
-// in increasing logL.
+// in increasing logL.  `own` (optional): each job's own best plan, already
+// known to the caller.
 bool plan_batch_groups(const std::vector<uint64_t>& ns, const std::vector<uint64_t>& ms, int policy,
-                       const CostModel& cm, std::vector<BatchGroup>* groups);
+                       const CostModel& cm, std::vector<BatchGroup>* groups,
+                       const std::vector<TilePlan>* own = nullptr);
 
 // One class for a whole batch: minimises the summed cost of every job's tiles.
 bool plan_batch(const std::vector<uint64_t>& ns, const std::vector<uint64_t>& ms, int policy,

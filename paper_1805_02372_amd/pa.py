@@ -36,6 +36,7 @@ PA_PREC_AUTO = 0x0000
 PA_PREC_FP32_SEG = 0x0010
 PA_PREC_FP64 = 0x0020
 PA_PREC_NTT = 0x0030
+PA_PREC_DIRECT = 0x0040
 PA_PREC_MASK = 0x00F0
 PA_NO_FALLBACK = 0x0100
 PA_ASYNC = 0x0200
@@ -54,7 +55,8 @@ class pa_stats(ctypes.Structure):
                 ("n2", ctypes.c_uint32), ("chunk_bits", ctypes.c_uint64), ("window_bits", ctypes.c_uint64),
                 ("tiles", ctypes.c_uint64), ("fallback_tiles", ctypes.c_uint64),
                 ("max_residual", ctypes.c_double), ("max_abs", ctypes.c_double), ("bound", ctypes.c_double),
-                ("ms_pass", ctypes.c_double * 4), ("model_bytes", ctypes.c_uint64), ("launches", ctypes.c_uint64)]
+                ("ms_pass", ctypes.c_double * 4), ("model_bytes", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("direct_jobs", ctypes.c_uint64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -66,7 +68,8 @@ class pa_plan(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_uint32), ("log2_len", ctypes.c_uint32), ("n1", ctypes.c_uint32),
                 ("n2", ctypes.c_uint32), ("chunk_bits", ctypes.c_uint64), ("window_bits", ctypes.c_uint64),
                 ("chunks", ctypes.c_uint64), ("windows", ctypes.c_uint64), ("bound", ctypes.c_double),
-                ("cost", ctypes.c_double)]
+                ("cost", ctypes.c_double), ("direct_cost", ctypes.c_double), ("direct", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -79,6 +82,8 @@ _sig = {
     "pa_hash": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, _P, _P, ctypes.c_uint32]),
     "pa_hash_batch": (ctypes.c_int, [_P, ctypes.POINTER(pa_job), ctypes.c_uint64, ctypes.c_uint32,
                                      ctypes.POINTER(ctypes.c_int)]),
+    "pa_hash_select": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, _P, _P, ctypes.c_uint64, _P,
+                                      ctypes.c_uint32]),
     "pa_seed_register": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint32,
                                         ctypes.POINTER(ctypes.c_uint32)]),
     "pa_submit": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, _P, _P,
@@ -173,6 +178,19 @@ def pa_hash_batch(ctx, jobs, flags: int = 0):
     per = (ctypes.c_int * max(1, len(jobs)))()
     st = _lib.pa_hash_batch(ctx, arr, len(jobs), int(flags), per)
     return st, [int(per[i]) for i in range(len(jobs))]
+
+
+def pa_hash_select(ctx, seed, n: int, m: int, key, idx, flags: int = 0):
+    """Output bits y[idx[k]] by the direct GF(2) product on the device.
+    seed/key: device tensors (PA_DEVICE_PTRS added) or host arrays; idx: a
+    sequence of indices < m.  Returns (status, uint8 array of bits)."""
+    if _is_device(seed) and _is_device(key):
+        flags |= PA_DEVICE_PTRS
+    ix = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64))
+    bits = np.zeros(len(ix), np.uint8)
+    st = _lib.pa_hash_select(ctx, _ptr(seed), int(n), int(m), _ptr(key), _ptr(ix) if len(ix) else None,
+                             len(ix), _ptr(bits) if len(ix) else None, int(flags))
+    return st, bits
 
 
 def pa_seed_register(ctx, seed, nbits: int, flags: int = 0) -> int:

@@ -1,0 +1,182 @@
+"""The direct word-parallel GF(2) path (PA_PREC_DIRECT, the AUTO choice for
+short outputs) and pa_hash_select, bit-exact against the CPU oracle, through
+the C ABI (MI355X)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pa():
+    from paper_1805_02372_amd import pa as _pa
+    return _pa
+
+
+@pytest.fixture(scope="module")
+def ctx(pa):
+    import torch
+    assert torch.cuda.is_available()
+    c = pa.pa_create(0, 0, None)
+    yield c
+    pa.pa_destroy(c)
+
+
+def _dev_job(p):
+    from gpu_util import to_dev, empty_dev
+    return (to_dev(p.seed), to_dev(p.key), empty_dev(synth.words_for(p.m)), p.n, p.m)
+
+
+# small, ragged (n mod 32, m mod 256 and m mod 64 at both ends), key much
+# shorter or much longer than the output
+SHAPES = [(1, 1), (1, 300_001), (2, 3), (31, 1), (32, 32), (33, 1), (63, 65), (64, 64), (65, 257),
+          (1000, 333), (4097, 511), (8191, 8193), (70_000, 255), (131_071, 513), (300_001, 64),
+          (1_000_003, 1), (2_000_001, 1000)]
+
+
+@pytest.mark.parametrize("n,m", SHAPES)
+def test_direct_vs_oracle(pa, ctx, n, m):
+    from gpu_util import gpu_hash, describe
+    rng = np.random.default_rng(n * 7919 + m)
+    p = synth.random_problem(rng, n, m)
+    print(f"direct n={n} m={m}", flush=True)
+    st, y = gpu_hash(pa, ctx, p.seed, n, m, p.key, pa.PA_PREC_DIRECT)
+    assert st == pa.PA_OK, pa.pa_strerror(st)
+    ref = oracle.hash_words(p.seed, n, m, p.key)
+    assert np.array_equal(y, ref), describe(y, ref, m)
+    s = pa.pa_last_stats(ctx)
+    assert s["prec"] == pa.PA_PREC_DIRECT and s["direct_jobs"] == 1 and s["tiles"] == 0
+
+
+@pytest.mark.parametrize("kind", ["ones", "period3", "sparse"])
+def test_direct_structured(pa, ctx, kind):
+    """Structured seeds and keys (all-ones, period 3, sparse): closed forms do
+    not depend on rounding here, the oracle is the reference."""
+    from gpu_util import gpu_hash, describe
+    n, m = 1_000_001, 3001
+    seed = synth.pattern_bits(kind, n + m - 1)
+    key = synth.pattern_bits(kind, n)
+    st, y = gpu_hash(pa, ctx, seed, n, m, key, pa.PA_PREC_DIRECT)
+    assert st == pa.PA_OK
+    ref = oracle.hash_words(seed, n, m, key)
+    assert np.array_equal(y, ref), describe(y, ref, m)
+
+
+def test_direct_c3_key_short_output(pa, ctx):
+    """The 12,345,679-bit key of the headline workload with 2000 outputs."""
+    from gpu_util import gpu_hash, describe
+    rng = np.random.default_rng(2)
+    p = synth.random_problem(rng, 12_345_679, 2000)
+    st, y = gpu_hash(pa, ctx, p.seed, p.n, p.m, p.key, pa.PA_PREC_DIRECT)
+    assert st == pa.PA_OK
+    ref = oracle.hash_words(p.seed, p.n, p.m, p.key)
+    assert np.array_equal(y, ref), describe(y, ref, p.m)
+
+
+def test_direct_equals_fft_paths(pa, ctx):
+    from gpu_util import gpu_hash
+    rng = np.random.default_rng(41)
+    p = synth.random_problem(rng, 1_000_000, 20_000)
+    outs = []
+    for f in (pa.PA_PREC_DIRECT, pa.PA_PREC_FP64, pa.PA_PREC_FP32_SEG):
+        st, y = gpu_hash(pa, ctx, p.seed, p.n, p.m, p.key, f)
+        assert st == pa.PA_OK
+        outs.append(y)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_auto_takes_direct_for_short_outputs(pa, ctx):
+    from gpu_util import gpu_hash
+    rng = np.random.default_rng(42)
+    for n, m, want in [(1_000_000, 256, True), (12_345_679, 1_234_567, False)]:
+        q = pa.pa_plan_query(n, m, pa.PA_PREC_AUTO)
+        assert bool(q["direct"]) == want, q
+        if n * m < 1e10:
+            p = synth.random_problem(rng, n, m)
+            st, y = gpu_hash(pa, ctx, p.seed, n, m, p.key, pa.PA_PREC_AUTO)
+            assert st == pa.PA_OK
+            assert pa.pa_last_stats(ctx)["prec"] == (pa.PA_PREC_DIRECT if want else pa.PA_PREC_FP32_SEG)
+            assert np.array_equal(y, oracle.hash_words(p.seed, n, m, p.key))
+
+
+def test_direct_timing_and_async(pa, ctx):
+    import torch
+    from gpu_util import from_dev
+    rng = np.random.default_rng(43)
+    p = synth.random_problem(rng, 500_000, 1000)
+    s, k, o, n, m = _dev_job(p)
+    assert pa.pa_hash(ctx, s, n, m, k, o, pa.PA_PREC_DIRECT | pa.PA_TIMING) == pa.PA_OK
+    st = pa.pa_last_stats(ctx)
+    assert st["ms_pass"][0] > 0 and st["launches"] >= 2, st
+    o2 = torch.full_like(o, -1)
+    assert pa.pa_hash(ctx, s, n, m, k, o2, pa.PA_PREC_DIRECT | pa.PA_ASYNC) == pa.PA_OK
+    assert pa.pa_hash(ctx, s, n, m, k, o, pa.PA_PREC_FP64) == pa.PA_OK   # synchronous, same stream
+    torch.cuda.synchronize()
+    assert np.array_equal(from_dev(o2), from_dev(o))
+
+
+@pytest.mark.parametrize("flags", ["direct", "auto"])
+def test_batch_with_direct_jobs(pa, ctx, flags):
+    """A batch whose jobs run on the direct path (all of them, or the short
+    outputs under AUTO) beside FFT groups; every job against the oracle."""
+    import torch
+    from gpu_util import from_dev
+    f = pa.PA_PREC_DIRECT if flags == "direct" else pa.PA_PREC_AUTO
+    rng = np.random.default_rng(44)
+    shapes = [(1, 1), (70, 3), (1_000_000, 100), (200_000, 10_000), (1_000_003, 300_001), (65, 257),
+              (2_000_000, 64)]
+    probs = [synth.random_problem(rng, n, m) for n, m in shapes]
+    dev = [_dev_job(p) for p in probs]
+    st, per = pa.pa_hash_batch(ctx, dev, f)
+    torch.cuda.synchronize()
+    assert st == pa.PA_OK and all(x == pa.PA_OK for x in per), (pa.pa_strerror(st), per)
+    s = pa.pa_last_stats(ctx)
+    want = sum(pa.pa_plan_query(p.n, p.m, f)["direct"] for p in probs)
+    assert s["direct_jobs"] == want and (flags == "auto" or want == len(probs)), s
+    assert flags == "direct" or 0 < want < len(probs)
+    for p, d in zip(probs, dev):
+        assert np.array_equal(from_dev(d[2])[: synth.words_for(p.m)],
+                              oracle.hash_words(p.seed, p.n, p.m, p.key)), (p.n, p.m)
+
+
+def test_direct_host_pointers(pa, ctx):
+    rng = np.random.default_rng(45)
+    p = synth.random_problem(rng, 77_777, 999)
+    out = np.zeros(synth.words_for(p.m), np.uint64)
+    assert pa.pa_hash(ctx, p.seed, p.n, p.m, p.key, out, pa.PA_PREC_DIRECT) == pa.PA_OK
+    assert np.array_equal(out, oracle.hash_words(p.seed, p.n, p.m, p.key))
+
+
+def test_select_vs_oracle_and_fft(pa, ctx):
+    """pa_hash_select on the headline workload: 4096 random outputs and both
+    ends, against the oracle and against the FFT result."""
+    from gpu_util import to_dev, gpu_hash
+    p = synth.single_config("c3")
+    st, y = gpu_hash(pa, ctx, p.seed, p.n, p.m, p.key, pa.PA_PREC_AUTO)
+    assert st == pa.PA_OK
+    idx = np.concatenate([[0, p.m - 1, 63, 64], np.random.default_rng(46).integers(0, p.m, 4096)])
+    st, bits = pa.pa_hash_select(ctx, to_dev(p.seed), p.n, p.m, to_dev(p.key), idx)
+    assert st == pa.PA_OK
+    assert np.array_equal(bits, oracle.hash_select(p.seed, p.n, p.m, p.key, idx))
+    assert np.array_equal(bits, synth.bits_to_array(y, p.m)[idx])
+
+
+def test_select_small_and_host(pa, ctx):
+    rng = np.random.default_rng(47)
+    for n, m in [(1, 1), (33, 5), (5000, 70_000), (100_000, 3)]:
+        p = synth.random_problem(rng, n, m)
+        idx = np.arange(m) if m <= 4096 else rng.integers(0, m, 4096)
+        st, bits = pa.pa_hash_select(ctx, p.seed, n, m, p.key, idx)   # host arrays
+        assert st == pa.PA_OK
+        assert np.array_equal(bits, oracle.hash_select(p.seed, n, m, p.key, idx)), (n, m)
+
+
+def test_select_rejects_bad_input(pa, ctx):
+    p = synth.random_problem(np.random.default_rng(48), 100, 10)
+    st, _ = pa.pa_hash_select(ctx, p.seed, 100, 10, p.key, [3, 10])
+    assert st == pa.PA_EINVAL
+    st, bits = pa.pa_hash_select(ctx, p.seed, 100, 10, p.key, [])
+    assert st == pa.PA_OK and bits.size == 0

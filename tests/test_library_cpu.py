@@ -119,7 +119,7 @@ def test_tile_geometry_reproduces_the_hash():
 
 def test_error_model_monotone(pa):
     f = pa.PA_PREC_FP32_SEG
-    v = [pa.pa_error_model(f, 20, b) for b in (1 << 10, 1 << 16, 1 << 20)]
+    v = [pa.pa_error_model(f, 20, b) for b in (1 << 10, 1 << 16, 1 << 19)]   # Bi <= L/2
     assert v[0] < v[1] < v[2]
     assert pa.pa_error_model(f, 24, 1 << 20) > pa.pa_error_model(f, 16, 1 << 20)
     assert pa.pa_error_model(pa.PA_PREC_FP64, 24, 1 << 24) < 1e-8
@@ -158,6 +158,21 @@ def test_error_model_covers_fp32_packed_convolution(pa):
     e01 = _fp32_packed_conv_error(np.random.default_rng(8), 20, 1 << 19, False)
     e_centred = _fp32_packed_conv_error(np.random.default_rng(8), 20, 1 << 19, True)
     assert e_centred * 1.5 < e01, (e01, e_centred)
+
+
+def test_direct_path_choice(pa):
+    """PA_PREC_DIRECT always takes the direct GF(2) path; AUTO takes it only
+    where its modeled cost (linear in m and in n) is below the FFT plan's."""
+    for n, m in SHAPES:
+        assert pa.pa_plan_query(n, m, pa.PA_PREC_DIRECT)["direct"] == 1
+        assert pa.pa_plan_query(n, m, pa.PA_PREC_FP32_SEG)["direct"] == 0
+        q = pa.pa_plan_query(n, m, pa.PA_PREC_AUTO)
+        assert q["direct"] == (1 if q["direct_cost"] < q["cost"] else 0)
+    assert pa.pa_plan_query(1_000_000, 100, 0)["direct"] == 1
+    assert pa.pa_plan_query(12_345_679, 1_234_567, 0)["direct"] == 0
+    c = [pa.pa_plan_query(1 << 20, m, 0)["direct_cost"] for m in (256, 512, 1024)]
+    assert c[0] < c[1] < c[2] and abs((c[2] - c[1]) - 2 * (c[1] - c[0])) < 1e-12
+    assert pa.pa_error_model(pa.PA_PREC_DIRECT, 20, 1000) == 0.0
 
 
 def test_plan_query_rejects_bad_input(pa):
