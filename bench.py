@@ -74,6 +74,7 @@ def run_single(pa, ctx, torch, prob, flags, steps, warmup):
     s = torch.from_numpy(prob.seed.view(np.int64).copy()).to("cuda:0")
     k = torch.from_numpy(prob.key.view(np.int64).copy()).to("cuda:0")
     o = torch.zeros(((prob.m + 63) // 64,), dtype=torch.int64, device="cuda:0")
+    torch.cuda.synchronize()   # the library's stream is not ordered after torch's
     for _ in range(warmup):
         st = pa.pa_hash(ctx, s, prob.n, prob.m, k, o, flags)
         assert st == pa.PA_OK, pa.pa_strerror(st)
@@ -110,6 +111,7 @@ def run_batch(pa, ctx, torch, jobs, flags, steps, warmup):
         k = torch.from_numpy(p.key.view(np.int64).copy()).to("cuda:0")
         o = torch.zeros(((p.m + 63) // 64,), dtype=torch.int64, device="cuda:0")
         dev.append((s, k, o, p.n, p.m))
+    torch.cuda.synchronize()
     for _ in range(warmup):
         st, per = pa.pa_hash_batch(ctx, dev, flags)
         assert st == pa.PA_OK, pa.pa_strerror(st)
@@ -142,6 +144,7 @@ def run_serving(pa, chk_ctx, torch, count: int, load: float = 0.7, budget_gib: i
     dseeds = [torch.from_numpy(sd.view(np.int64).copy()).to("cuda:0") for sd in seeds]
     dkeys = [torch.from_numpy(k.view(np.int64).copy()).to("cuda:0") for k in keys]
     outs = [torch.empty(((r["m"] + 63) // 64,), dtype=torch.int64, device="cuda:0") for r in reqs]
+    torch.cuda.synchronize()
     mean_n = float(np.mean([r["n"] for r in reqs]))
     spacing = reqs[-1]["t"] / len(reqs)          # synth arrivals are at 100/s; rescaled below
 
@@ -284,6 +287,45 @@ def run_table1(pa, ctx, torch, reps: int = 5):
     return out
 
 
+def run_stream_leg(pa, ctx, torch, n: int = 128_000_000, m: int = 1_000_000, block: int = 16_000_000):
+    """Block-serial hashing from host memory (the paper's Fig. 1-3 flow): a
+    128 Mbit key with m = 10^6, fed in 16 Mbit blocks through pa_stream_feed
+    (each block's key bits and seed slice copied over PCIe, hashed, XOR-merged
+    on the device).  The rate includes the copies.  Checked on 256 outputs by
+    pa_hash_select with the whole seed and key in device memory."""
+    import synth
+    rng = np.random.default_rng(9)
+    prob = synth.random_problem(rng, n, m)
+    keyb = synth.bits_to_array(prob.key, n)
+    seedb = synth.bits_to_array(prob.seed, n + m - 1)
+    blocks = []
+    for lo in range(0, n, block):
+        ln = min(block, n - lo)
+        blocks.append((lo, ln, synth.array_to_bits(keyb[lo:lo + ln]),
+                       synth.array_to_bits(seedb[n - lo - ln:n - lo + m - 1])))
+    out = np.zeros(synth.words_for(m), np.uint64)
+    times = []
+    for rep in range(3):
+        t0 = time.perf_counter()
+        st, h = pa.pa_stream_open(ctx, n, m, pa.PA_PREC_AUTO)
+        assert st == pa.PA_OK, pa.pa_strerror(st)
+        for lo, ln, kb, sb in blocks:
+            st = pa.pa_stream_feed(h, kb, lo, ln, sb)
+            assert st == pa.PA_OK, pa.pa_strerror(st)
+        st = pa.pa_stream_close(h, out)
+        assert st == pa.PA_OK, pa.pa_strerror(st)
+        times.append(time.perf_counter() - t0)
+    el = float(np.median(times))
+    s = torch.from_numpy(prob.seed.view(np.int64).copy()).to("cuda:0")
+    k = torch.from_numpy(prob.key.view(np.int64).copy()).to("cuda:0")
+    idx = rng.integers(0, m, 256)
+    st, ref = pa.pa_hash_select(ctx, s, n, m, k, idx)
+    assert st == pa.PA_OK
+    return {"n": n, "m": m, "block_bits": block, "blocks": len(blocks), "source": "host memory (PCIe)",
+            "gbps_including_copies": round(n / el / 1e9, 3), "ms": round(el * 1e3, 3),
+            "spot_check_exact": bool(np.array_equal(ref, synth.bits_to_array(out, m)[idx]))}
+
+
 def cpu_baseline(prob, target_s: float = 12.0):
     """Oracle on a prefix of the outputs (full key): by the constant diagonals
     y[0:m'] is the hash with seed bits [0, n+m'-1) and m' outputs; its cost is
@@ -316,6 +358,7 @@ def main():
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None, help="run one path only (profiling)")
     ap.add_argument("--no-direct", action="store_true", help="skip the direct-path (short output) leg")
     ap.add_argument("--no-table1", action="store_true", help="skip the 4-128 Mbit sweep")
+    ap.add_argument("--no-stream", action="store_true", help="skip the block-serial host streaming leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 512 MiB device copy (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -369,6 +412,10 @@ def main():
     table1 = None
     if not args.only and not args.no_table1:
         table1 = run_table1(pa, ctx, torch)
+    stream = None
+    if not args.only and not args.no_stream:
+        stream = run_stream_leg(pa, ctx, torch)
+        log(f"[bench] block-serial stream from host: {stream}")
 
     serving = None
     if args.serve and not args.only:
@@ -456,6 +503,8 @@ def main():
         line["direct_short_output"] = direct
     if table1 is not None:
         line["table1_sweep"] = table1
+    if stream is not None:
+        line["block_serial_host"] = stream
     if serving is not None:
         line["serving_c5"] = serving
     if not args.no_cpu:

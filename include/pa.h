@@ -21,7 +21,9 @@
  * Memory: unless PA_DEVICE_PTRS is given, seed/key/out are host pointers and
  * the call copies them (and the call is synchronous).  With PA_DEVICE_PTRS they
  * are device pointers on the context's device (e.g. a torch tensor's
- * data_ptr()).  The caller owns seed, key and out and keeps them alive until the
+ * data_ptr()).  The context's stream is not ordered after other streams:
+ * device buffers written on another stream must be complete (synchronized,
+ * or the context created on that stream) before a call uses them.  The caller owns seed, key and out and keeps them alive until the
  * call has completed; out must not overlap seed or key.  The library owns its
  * workspace, plans, twiddle tables, tuning data and copies of registered
  * seeds.
@@ -116,6 +118,45 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs, uint64_t count, uint32_
  * or count > 2^20. */
 pa_status pa_hash_select(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, const uint64_t* key,
                          const uint64_t* idx, uint64_t count, uint8_t* bits, uint32_t flags);
+
+/* ---- block-serial hashing (section 3, Fig. 1-3, Eq. 4-7) --------------------
+ * The key arrives in blocks, from host or device memory, and each block's
+ * partial hash is XOR-accumulated into an m-bit accumulator kept in device
+ * memory.  Key bits [lo, lo+len) meet only seed bits [n-lo-len, n-lo+m-1)
+ * (len+m-1 bits): the block's partial hash is the hash of that seed slice with
+ * the block (Eq. 4-6), and the hash of the key is the XOR of the partial
+ * hashes of blocks that cover it once (Eq. 7).  Blocks may come in any order
+ * and have any lengths.  The accumulator can be read and restored, so a job
+ * can resume at any block boundary. */
+typedef struct pa_stream pa_stream;
+
+/* Open a stream for an (n, m) job.  flags: the precision bits used for every
+ * block (as for pa_hash) and PA_DEVICE_PTRS when the pointers given to
+ * pa_stream_feed / _state / _resume / _close are device pointers.  The
+ * accumulator starts at zero.  PA_EINVAL for n == 0, m == 0 or NULL;
+ * PA_ENOMEM when the accumulator does not fit the context's budget. */
+pa_status pa_stream_open(pa_ctx* ctx, uint64_t n, uint64_t m, uint32_t flags, pa_stream** stream);
+
+/* XOR the partial hash of key bits [lo, lo+len) into the accumulator.
+ * key_block: len bits, bit 0 = key bit lo.  seed_block: len+m-1 bits, bit 0 =
+ * seed bit n-lo-len.  Synchronous (the inputs may be reused on return).
+ * PA_EINVAL for len == 0, lo+len > n or NULL pointers; errors of pa_hash
+ * otherwise (the accumulator is then unchanged). */
+pa_status pa_stream_feed(pa_stream* stream, const uint64_t* key_block, uint64_t lo, uint64_t len,
+                         const uint64_t* seed_block);
+
+/* Copy the accumulator (ceil(m/64) words) to acc and the number of key bits
+ * fed so far to *fed_bits (either may be NULL).  Synchronous. */
+pa_status pa_stream_state(pa_stream* stream, uint64_t* acc, uint64_t* fed_bits);
+
+/* Replace the accumulator by acc (ceil(m/64) words, e.g. a saved state) and
+ * the fed-bit count by fed_bits.  PA_EINVAL for fed_bits > n or NULL acc. */
+pa_status pa_stream_resume(pa_stream* stream, const uint64_t* acc, uint64_t fed_bits);
+
+/* Write the hash (m bits) to out unless out is NULL, and free the stream.
+ * With out != NULL, PA_EINVAL (and nothing written) unless exactly n key bits
+ * were fed.  The stream is freed in every case. */
+pa_status pa_stream_close(pa_stream* stream, uint64_t* out);
 
 /* ---- serving (continuous batching) --------------------------------------- */
 

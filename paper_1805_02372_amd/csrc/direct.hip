@@ -125,7 +125,20 @@ k_direct_select(const uint32_t* __restrict__ seed32, uint64_t sw32, const uint32
     if ((tid & 63) == 0 && bal) atomicXor((unsigned long long*)&res[g0 >> 6], bal);
 }
 
+__global__ void __launch_bounds__(kDirectThreads)
+k_xor_words(uint64_t* dst, const uint64_t* src, uint64_t words) {   // src may be dst (clears it)
+    const uint64_t g = (uint64_t)blockIdx.x * kDirectThreads + threadIdx.x;
+    if (g < words) dst[g] ^= src[g];
+}
+
 static uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+int launch_xor_words(uint64_t* dst, const uint64_t* src, uint64_t words, void* stream) {
+    if (words == 0) return 0;
+    hipLaunchKernelGGL(k_xor_words, dim3((uint32_t)cdiv(words, kDirectThreads)), dim3(kDirectThreads), 0,
+                       (hipStream_t)stream, dst, src, words);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
 
 uint64_t direct_key_words(uint64_t n) { return cdiv(cdiv(n, 32), 4) * 4; }
 

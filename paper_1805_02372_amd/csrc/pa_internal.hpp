@@ -83,6 +83,9 @@ int launch_direct(const uint64_t* seed, const uint64_t* key, uint64_t n, uint64_
 int launch_direct_select(const uint64_t* seed, const uint64_t* key, uint64_t n, uint64_t m, const uint64_t* idx,
                          uint32_t count, uint64_t* res, uint32_t* kr, void* stream);
 
+// dst[k] ^= src[k] for k < words (stream order).  Returns 0, or -1.
+int launch_xor_words(uint64_t* dst, const uint64_t* src, uint64_t words, void* stream);
+
 // Registered by the per-precision kernel objects.
 const ClassKernels* class_kernels(int prec, int logL);
 

@@ -84,6 +84,11 @@ _sig = {
                                      ctypes.POINTER(ctypes.c_int)]),
     "pa_hash_select": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, _P, _P, ctypes.c_uint64, _P,
                                       ctypes.c_uint32]),
+    "pa_stream_open": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(_P)]),
+    "pa_stream_feed": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, _P]),
+    "pa_stream_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_uint64)]),
+    "pa_stream_resume": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
+    "pa_stream_close": (ctypes.c_int, [_P, _P]),
     "pa_seed_register": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint32,
                                         ctypes.POINTER(ctypes.c_uint32)]),
     "pa_submit": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, _P, _P,
@@ -191,6 +196,34 @@ def pa_hash_select(ctx, seed, n: int, m: int, key, idx, flags: int = 0):
     st = _lib.pa_hash_select(ctx, _ptr(seed), int(n), int(m), _ptr(key), _ptr(ix) if len(ix) else None,
                              len(ix), _ptr(bits) if len(ix) else None, int(flags))
     return st, bits
+
+
+def pa_stream_open(ctx, n: int, m: int, flags: int = 0):
+    """Block-serial hashing of an (n, m) job.  Returns (status, stream)."""
+    h = _P()
+    st = _lib.pa_stream_open(ctx, int(n), int(m), int(flags), ctypes.byref(h))
+    return st, h
+
+
+def pa_stream_feed(stream, key_block, lo: int, length: int, seed_block) -> int:
+    """XOR the partial hash of key bits [lo, lo+length) into the accumulator
+    (seed_block: seed bits [n-lo-length, n-lo+m-1))."""
+    return _lib.pa_stream_feed(stream, _ptr(key_block), int(lo), int(length), _ptr(seed_block))
+
+
+def pa_stream_state(stream, acc=None):
+    """Copy the accumulator into acc (if given); returns (status, fed_bits)."""
+    fed = ctypes.c_uint64(0)
+    st = _lib.pa_stream_state(stream, _ptr(acc) if acc is not None else None, ctypes.byref(fed))
+    return st, int(fed.value)
+
+
+def pa_stream_resume(stream, acc, fed_bits: int) -> int:
+    return _lib.pa_stream_resume(stream, _ptr(acc), int(fed_bits))
+
+
+def pa_stream_close(stream, out=None) -> int:
+    return _lib.pa_stream_close(stream, _ptr(out) if out is not None else None)
 
 
 def pa_seed_register(ctx, seed, nbits: int, flags: int = 0) -> int:

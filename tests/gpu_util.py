@@ -16,7 +16,9 @@ def torch_cuda():
 def to_dev(words: np.ndarray):
     torch = torch_cuda()
     a = np.ascontiguousarray(words, dtype=np.uint64).view(np.int64)
-    return torch.from_numpy(a.copy()).to("cuda:0")
+    t = torch.from_numpy(a.copy()).to("cuda:0")
+    torch.cuda.synchronize()   # the library's stream is not ordered after torch's
+    return t
 
 
 def from_dev(t) -> np.ndarray:
@@ -26,7 +28,9 @@ def from_dev(t) -> np.ndarray:
 def empty_dev(words: int, fill: int = -1):
     torch = torch_cuda()
     # filled with ones so that untouched words are caught
-    return torch.full((max(1, words),), fill, dtype=torch.int64, device="cuda:0")
+    t = torch.full((max(1, words),), fill, dtype=torch.int64, device="cuda:0")
+    torch.cuda.synchronize()   # the fill must land before the library's stream writes
+    return t
 
 
 def gpu_hash(pa, ctx, seed, n, m, key, flags=0):

@@ -47,6 +47,8 @@ def test_direct_vs_oracle(pa, ctx, n, m):
     assert st == pa.PA_OK, pa.pa_strerror(st)
     ref = oracle.hash_words(p.seed, n, m, p.key)
     assert np.array_equal(y, ref), describe(y, ref, m)
+    if n * m <= 10**8:   # also the bit-loop oracle, which is not word-parallel
+        assert np.array_equal(y, oracle.hash_bits(p.seed, n, m, p.key))
     s = pa.pa_last_stats(ctx)
     assert s["prec"] == pa.PA_PREC_DIRECT and s["direct_jobs"] == 1 and s["tiles"] == 0
 
@@ -112,6 +114,7 @@ def test_direct_timing_and_async(pa, ctx):
     st = pa.pa_last_stats(ctx)
     assert st["ms_pass"][0] > 0 and st["launches"] >= 2, st
     o2 = torch.full_like(o, -1)
+    torch.cuda.synchronize()   # the fill lands before the library's stream writes
     assert pa.pa_hash(ctx, s, n, m, k, o2, pa.PA_PREC_DIRECT | pa.PA_ASYNC) == pa.PA_OK
     assert pa.pa_hash(ctx, s, n, m, k, o, pa.PA_PREC_FP64) == pa.PA_OK   # synchronous, same stream
     torch.cuda.synchronize()
