@@ -154,10 +154,12 @@ int launch_direct(const uint64_t* seed, const uint64_t* key, uint64_t n, uint64_
                        kr, kw4, out, ow);
     if (hipGetLastError() != hipSuccess) return -1;
     *launches += 1;
-    // enough workgroups to fill the chip: split the key when the outputs are few
+    // about 1024 workgroups (4 per CU), each with at least 1024 key words:
+    // split the key when the outputs are few (measured on MI355X against
+    // 512..8192 workgroups and 256-word chunks)
     const uint64_t bx = cdiv(m, kDirectThreads);
-    const uint64_t want_y = std::max<uint64_t>(1, cdiv(2048, bx));
-    uint64_t kc = std::max<uint64_t>(256, cdiv(kw4, want_y));
+    const uint64_t want_y = std::max<uint64_t>(1, cdiv(1024, bx));
+    uint64_t kc = std::max<uint64_t>(1024, cdiv(kw4, want_y));
     kc = std::min<uint64_t>(cdiv(kc, 4) * 4, kDirectChunk);
     const uint64_t by = cdiv(kw4, kc);
     for (uint64_t x0 = 0; x0 < bx; x0 += kSlabX)
