@@ -100,8 +100,10 @@ typedef struct {
  * all its tiles.  The groups run concurrently on the context's stream and on
  * PA_BATCH_LANES - 1 side streams of the context (default 3 streams in all),
  * forked from the context's stream.  Tile and segment sizes come from the cost
- * model (tuned when pa_tune ran).  pa_last_stats then names the largest class
- * used.
+ * model (tuned when pa_tune ran).  Jobs that the precision bits put on the
+ * direct path (PA_PREC_DIRECT, or PA_PREC_AUTO where it is modeled cheaper)
+ * run on the context's stream beside the groups.  pa_last_stats then names
+ * the largest class used and counts the direct jobs.
  * per_job (optional, count entries) receives each job's status; the return
  * value is PA_OK only if every job succeeded.  Pointer kind per PA_DEVICE_PTRS
  * as for pa_hash.  Synchronous. */
@@ -225,9 +227,12 @@ const char* pa_strerror(pa_status status);
  * one named), with `reps` timed runs each on synthetic bits, and use the
  * results in this context's planner.  Each class runs one launch with one tile
  * and one with four: the marginal cost per tile goes to the class and the
- * remainder (median over classes) to the per-launch cost.  If path is not NULL
- * the table is also written there as JSON ({"launch": seconds, "fp32": {"12":
- * seconds, ...}, ...}).  Synchronous; PA_EDEVICE on a HIP error, PA_EINVAL for
+ * remainder (median over classes) to the per-launch cost.  With PA_PREC_AUTO
+ * or PA_PREC_DIRECT it also times the direct GF(2) path at two output lengths
+ * and takes the slope as its cost per output and key word (PA_PREC_DIRECT
+ * times only that).  If path is not NULL the table is also written there as
+ * JSON ({"launch": seconds, "direct": seconds, "fp32": {"12": seconds, ...},
+ * ...}).  Synchronous; PA_EDEVICE on a HIP error, PA_EINVAL for
  * a file that cannot be written. */
 pa_status pa_tune(pa_ctx* ctx, uint32_t flags, int reps, const char* path);
 

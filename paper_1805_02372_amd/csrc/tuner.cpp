@@ -29,7 +29,7 @@ static const char* prec_key(int prec) { return prec == PREC_FP32 ? "fp32" : prec
 static pa_status save_json(const CostModel& cm, const std::vector<int>& precs, const char* path) {
     FILE* f = fopen(path, "w");
     if (!f) return PA_EINVAL;
-    fprintf(f, "{\"launch\": %.9g", cm.launch_s);
+    fprintf(f, "{\"launch\": %.9g, \"direct\": %.9g", cm.launch_s, cm.direct_s);
     for (size_t i = 0; i < precs.size(); ++i) {
         fprintf(f, ", \"%s\": {", prec_key(precs[i]));
         for (int k = 12; k <= 24; ++k) fprintf(f, "%s\"%d\": %.9g", k > 12 ? ", " : "", k, cm.tile(precs[i], k));
@@ -53,6 +53,14 @@ static pa_status load_json(CostModel& cm, const char* path) {
     if (la != std::string::npos) {
         const double v = strtod(text.c_str() + la + 9, nullptr);
         if (v >= 0 && v < 1.0) cm.launch_s = v;
+    }
+    const size_t di = text.find("\"direct\":");
+    if (di != std::string::npos) {
+        const double v = strtod(text.c_str() + di + 9, nullptr);
+        if (v > 0 && v < 1e-6) {
+            cm.direct_s = v;
+            ++loaded;
+        }
     }
     for (int prec : {PREC_FP32, PREC_FP64, PREC_NTT}) {
         const std::string tag = std::string("\"") + prec_key(prec) + "\"";
@@ -105,6 +113,7 @@ pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path) {
         case PA_PREC_FP32_SEG: precs = {PREC_FP32}; break;
         case PA_PREC_FP64: precs = {PREC_FP64}; break;
         case PA_PREC_NTT: precs = {PREC_NTT}; break;
+        case PA_PREC_DIRECT: break;   // the direct path only
         default: return PA_EINVAL;
     }
     if (reps < 1) reps = 1;
@@ -148,6 +157,29 @@ pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path) {
             cm.set(prec, k, marginal);
             fixed.push_back(std::max(t1 - marginal, 0.0));
         }
+    // direct path: the slope between two output lengths at n = 2^22 is the
+    // cost per output and 32-bit key word
+    const uint32_t pbits = flags & PA_PREC_MASK;
+    if (pbits == PA_PREC_AUTO || pbits == PA_PREC_DIRECT) {
+        const uint64_t n = 1ull << 22, ms[2] = {1024, 4096};
+        double t[2] = {1e30, 1e30};
+        for (int q = 0; q < 2 && st == PA_OK; ++q)
+            for (int r = 0; r <= reps && st == PA_OK; ++r) {
+                pa_stats ps{};
+                c->main.timer.reset();
+                st = c->main.direct(c, dseed, dkey, n, ms[q], douts, true, &ps);
+                if (st == PA_OK && hipStreamSynchronize(c->main.stream) != hipSuccess) st = PA_EDEVICE;
+                c->main.timer.collect(ps.ms_pass);
+                if (r > 0 && ps.ms_pass[0] > 0) t[q] = std::min(t[q], ps.ms_pass[0] * 1e-3);
+            }
+        if (st != PA_OK) {
+            buf.release(c);
+            return st;
+        }
+        const double words = (double)((n / 32 + 3) / 4 * 4);
+        const double slope = (t[1] - t[0]) / ((double)(ms[1] - ms[0]) * words);
+        if (t[1] < 1e30 && slope > 0) cm.direct_s = slope;
+    }
     buf.release(c);
     if (!fixed.empty()) {
         std::sort(fixed.begin(), fixed.end());

@@ -183,3 +183,26 @@ def test_select_rejects_bad_input(pa, ctx):
     assert st == pa.PA_EINVAL
     st, bits = pa.pa_hash_select(ctx, p.seed, 100, 10, p.key, [])
     assert st == pa.PA_OK and bits.size == 0
+
+
+def test_tune_measures_direct_cost(pa, tmp_path):
+    """pa_tune with PA_PREC_DIRECT times only the direct path; the measured
+    cost per output and key word is written, loaded, and used by AUTO."""
+    import json
+    c = pa.pa_create(0, 0, None)
+    try:
+        path = str(tmp_path / "direct.json")
+        assert pa.pa_tune(c, pa.PA_PREC_DIRECT, 2, path) == pa.PA_OK
+        d = json.load(open(path))["direct"]
+        assert 1e-15 < d < 1e-11, d   # seconds per output and 32-bit key word
+        c2 = pa.pa_create(0, 0, None)
+        try:
+            assert pa.pa_tune_load(c2, path) == pa.PA_OK
+            from gpu_util import gpu_hash
+            p = synth.random_problem(np.random.default_rng(49), 2_000_000, 300)
+            st, y = gpu_hash(pa, c2, p.seed, p.n, p.m, p.key, pa.PA_PREC_AUTO)
+            assert st == pa.PA_OK and np.array_equal(y, oracle.hash_words(p.seed, p.n, p.m, p.key))
+        finally:
+            pa.pa_destroy(c2)
+    finally:
+        pa.pa_destroy(c)

@@ -285,6 +285,7 @@ def test_tune_writes_and_loads(pa, ctx, tmp_path):
     path = str(tmp_path / "tune.json")
     assert pa.pa_tune(ctx, pa.PA_PREC_FP32_SEG, 1, path) == pa.PA_OK
     data = json.load(open(path))
+    assert data["direct"] > 0   # the built-in direct-path cost (not timed for FP32_SEG)
     costs = [data["fp32"][str(k)] for k in range(12, 25)]
     assert all(c > 0 for c in costs)
     assert 0 <= data["launch"] < 1e-2   # per-launch cost in seconds
