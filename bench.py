@@ -364,8 +364,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print(json.dumps({"error": "single-GPU build: the path runs on one GPU; "
-                                   "sharding is described in DESIGN.md, --gpus must be 1"}))
+        print(json.dumps({"error": "the hash runs on one GPU here (how it would shard is a design note); "
+                                   "--gpus must be 1"}))
         sys.exit(2)
 
     import torch
