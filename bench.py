@@ -30,6 +30,9 @@ import numpy as np  # noqa: E402
 METRIC = "input-key Gbps (bit-exact) at n=1e7; batched FP32 vs plain FP64 path, p99 latency"
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_c3.json")
+PROFILE_VALU = os.path.join(ROOT, "profiles", "valu_c3.json")
+# vector instructions a CU issues per second: 4 SIMDs, one 64-lane instruction each per 4 cycles
+VALU_WAVE_INSTR_PEAK = 256 * 2.4e9
 
 
 def log(*a):
@@ -452,6 +455,15 @@ def main():
         tr = json.load(open(PROFILE_TRAFFIC))
         if tr.get("kernel_digest") == kernel_source_digest():
             traffic = tr.get("bytes_per_launch", {}).get(f"pass{dom + 1}")
+    valu = None   # the same kernel against the vector-ALU issue rate (counters of the same sources)
+    if head_name == "fp32" and os.path.exists(PROFILE_VALU):
+        vc = json.load(open(PROFILE_VALU))
+        instr = vc.get("valu_wave_instructions_per_launch", {}).get(f"pass{dom + 1}")
+        if vc.get("kernel_digest") == kernel_source_digest() and instr:
+            rate = instr / (kms[dom] * 1e-3)
+            valu = {"bound": "alu", "kernel": f"pass{dom + 1}", "achieved": round(rate / 1e9, 1),
+                    "peak": round(VALU_WAVE_INSTR_PEAK / 1e9, 1), "unit": "G wave-instructions/s",
+                    "frac": round(rate / VALU_WAVE_INSTR_PEAK, 4), "instructions": instr}
     pipeline_ms = sum(kms)
     line = {
         "metric": METRIC,
@@ -479,6 +491,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel_ms": round(kms[dom], 5), "bytes_per_launch": round(pb[dom]),
         },
+        "roofline_valu": valu,
         "pipeline": {
             "kernel_ms": [round(x, 5) for x in head["kernel_ms"]],
             "model_bytes": st["model_bytes"],
