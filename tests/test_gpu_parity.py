@@ -164,3 +164,30 @@ def test_invalid_arguments(pa, ctx):
     assert pa.pa_hash(ctx, s, 5, 0, k, o, 0) == pa.PA_EINVAL
     assert pa.pa_hash(ctx, 0, 5, 5, k, o, pa.PA_DEVICE_PTRS) == pa.PA_EINVAL
     assert pa.pa_hash(ctx, s, 5, 5, k, o, 0x00F0) == pa.PA_EINVAL
+
+
+def _random_shapes(count=24, seed=2027):
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        n = int(10 ** rng.uniform(0, 6.5))
+        m = int(10 ** rng.uniform(0, 6.5))
+        if n * m <= 2e11:   # the oracle stays well under a second
+            out.append((max(1, n), max(1, m)))
+    return out
+
+
+@pytest.mark.parametrize("n,m", _random_shapes())
+def test_random_shapes_every_path(pa, ctx, n, m):
+    """Log-uniform random shapes (1 .. 3e6 bits each side), every precision
+    path against the oracle: FP32 tiles, plain FP64, NTT, the direct product
+    and AUTO's choice."""
+    from gpu_util import describe
+    rng = np.random.default_rng(n * 31 + m)
+    p = synth.random_problem(rng, n, m)
+    ref = oracle.hash_words(p.seed, n, m, p.key)
+    for prec in ("fp32", "fp64", "ntt", "direct", "auto"):
+        flags = pa.PA_PREC_DIRECT if prec == "direct" else _flags(pa, prec)
+        st, y = _run(pa, ctx, p, flags)
+        assert st == pa.PA_OK, (prec, pa.pa_strerror(st))
+        assert np.array_equal(y, ref), f"{prec}: " + describe(y, ref, m)
