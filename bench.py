@@ -247,7 +247,7 @@ def run_direct_leg(pa, ctx, torch, steps, warmup, m: int = 1000):
     rf = run_single(pa, ctx, torch, prob, pa.PA_PREC_FP32_SEG, steps, warmup)
     key_words = -(-(-(-prob.n // 32)) // 4) * 4          # ceil(n / 32) rounded up to 4
     steps_word = (-(-m // 256) * 256) * key_words       # outputs in blocks of 256
-    kms = rd["kernel_ms"][0]
+    kms = rd["kernel_ms"][1]   # the product kernel (ms_pass[0] is the key-reversal prep)
     ops = 2.0 * steps_word / (kms * 1e-3)
     return {"n": prob.n, "m": m,
             "direct_gbps": round(prob.n * steps / rd["elapsed"] / 1e9, 3),

@@ -200,7 +200,8 @@ typedef struct {
     double max_abs;           /* max |z| over all outputs                     */
     double bound;             /* predicted max error of the plan              */
     double ms_pass[4];        /* PA_TIMING: summed kernel ms of pass 1, 2, 3; [3] is 0
-                                 (key chunks are XOR-merged inside pass 3)  */
+                                 (key chunks are XOR-merged inside pass 3).
+                                 Direct path: [0] key reversal, [1] product */
     uint64_t model_bytes;     /* algorithmic HBM bytes of the FFT passes (direct
                                  path: seed, key and output once)             */
     uint64_t launches;        /* kernel launches                              */

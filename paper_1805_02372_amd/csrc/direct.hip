@@ -19,7 +19,7 @@
 
 #include <algorithm>
 
-#include "pa_internal.hpp"
+#include "direct.hpp"
 
 namespace pa {
 
@@ -145,15 +145,21 @@ uint64_t direct_key_words(uint64_t n) { return cdiv(cdiv(n, 32), 4) * 4; }
 // Grid slabs: at most 2^20 workgroups along x and 2^15 along y per launch.
 constexpr uint64_t kSlabX = 1ull << 20, kSlabY = 1ull << 15;
 
-int launch_direct(const uint64_t* seed, const uint64_t* key, uint64_t n, uint64_t m, uint64_t* out, uint32_t* kr,
-                  void* stream, uint64_t* launches) {
-    hipStream_t s = (hipStream_t)stream;
-    const uint64_t kw4 = direct_key_words(n), ow = cdiv(m, 64), sw32 = 2 * cdiv(n + m - 1, 64);
+int launch_direct_prep(const uint64_t* key, uint64_t n, uint64_t m, uint64_t* out, uint32_t* kr, void* stream,
+                       uint64_t* launches) {
+    const uint64_t kw4 = direct_key_words(n), ow = cdiv(m, 64);
     const uint64_t prep = std::max(kw4, ow);
-    hipLaunchKernelGGL(k_direct_prep, dim3((uint32_t)cdiv(prep, kDirectThreads)), dim3(kDirectThreads), 0, s, key, n,
-                       kr, kw4, out, ow);
+    hipLaunchKernelGGL(k_direct_prep, dim3((uint32_t)cdiv(prep, kDirectThreads)), dim3(kDirectThreads), 0,
+                       (hipStream_t)stream, key, n, kr, kw4, out, ow);
     if (hipGetLastError() != hipSuccess) return -1;
     *launches += 1;
+    return 0;
+}
+
+int launch_direct_main(const uint64_t* seed, uint64_t n, uint64_t m, uint64_t* out, const uint32_t* kr,
+                       void* stream, uint64_t* launches) {
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t kw4 = direct_key_words(n), sw32 = 2 * cdiv(n + m - 1, 64);
     // about 1024 workgroups (4 per CU), each with at least 1024 key words:
     // split the key when the outputs are few (measured on MI355X against
     // 512..8192 workgroups and 256-word chunks)
@@ -165,8 +171,8 @@ int launch_direct(const uint64_t* seed, const uint64_t* key, uint64_t n, uint64_
     for (uint64_t x0 = 0; x0 < bx; x0 += kSlabX)
         for (uint64_t y0 = 0; y0 < by; y0 += kSlabY) {
             const dim3 grid((uint32_t)std::min(kSlabX, bx - x0), (uint32_t)std::min(kSlabY, by - y0));
-            hipLaunchKernelGGL(k_direct, grid, dim3(kDirectThreads), 0, s, (const uint32_t*)seed, sw32,
-                               (const uint32_t*)kr, kw4, y0 * kc, (uint32_t)kc, x0 * kDirectThreads, m, out);
+            hipLaunchKernelGGL(k_direct, grid, dim3(kDirectThreads), 0, s, (const uint32_t*)seed, sw32, kr, kw4,
+                               y0 * kc, (uint32_t)kc, x0 * kDirectThreads, m, out);
             if (hipGetLastError() != hipSuccess) return -1;
             *launches += 1;
         }

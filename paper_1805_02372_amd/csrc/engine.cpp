@@ -17,6 +17,7 @@
 #include "planner.hpp"
 #include "tables.hpp"
 #include "engine.hpp"
+#include "direct.hpp"
 
 using namespace pa;
 
@@ -438,9 +439,15 @@ pa_status Lane::direct(Ctx* c, const uint64_t* seed, const uint64_t* key, uint64
                        bool timing, pa_stats* stats) {
     pa_status st = aux.ensure(c, direct_key_words(n) * 4);
     if (st != PA_OK) return st;
+    // PA_TIMING: ms_pass[0] the prep kernel, ms_pass[1] the product kernels
     hipEvent_t a = timing ? timer.mark(stream) : nullptr;
-    if (launch_direct(seed, key, n, m, out, (uint32_t*)aux.ptr, stream, &stats->launches)) return PA_EDEVICE;
-    if (timing) timer.spans.push_back({0, {a, timer.mark(stream)}});
+    if (launch_direct_prep(key, n, m, out, (uint32_t*)aux.ptr, stream, &stats->launches)) return PA_EDEVICE;
+    hipEvent_t b = timing ? timer.mark(stream) : nullptr;
+    if (launch_direct_main(seed, n, m, out, (const uint32_t*)aux.ptr, stream, &stats->launches)) return PA_EDEVICE;
+    if (timing) {
+        timer.spans.push_back({0, {a, b}});
+        timer.spans.push_back({1, {b, timer.mark(stream)}});
+    }
     stats->direct_jobs += 1;
     stats->model_bytes += (words_of(n + m - 1) + words_of(n) + words_of(m)) * 8;
     return PA_OK;

@@ -73,19 +73,6 @@ struct ClassKernels {
     launch_fn pass1, pass2, pass3;
 };
 
-// Direct GF(2) path (direct.hip).  kr: device scratch of direct_key_words(n)
-// 32-bit words (the reversed key).  launch_direct writes all of out (m bits);
-// launch_direct_select writes bit k of res (ceil(count/64) words) = y[idx[k]].
-// Both return 0, or -1 on a launch error.
-uint64_t direct_key_words(uint64_t n);
-int launch_direct(const uint64_t* seed, const uint64_t* key, uint64_t n, uint64_t m, uint64_t* out, uint32_t* kr,
-                  void* stream, uint64_t* launches);
-int launch_direct_select(const uint64_t* seed, const uint64_t* key, uint64_t n, uint64_t m, const uint64_t* idx,
-                         uint32_t count, uint64_t* res, uint32_t* kr, void* stream);
-
-// dst[k] ^= src[k] for k < words (stream order).  Returns 0, or -1.
-int launch_xor_words(uint64_t* dst, const uint64_t* src, uint64_t words, void* stream);
-
 // Registered by the per-precision kernel objects.
 const ClassKernels* class_kernels(int prec, int logL);
 

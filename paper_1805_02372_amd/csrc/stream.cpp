@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 
+#include "direct.hpp"
 #include "engine.hpp"
 
 using namespace pa;

@@ -170,7 +170,8 @@ pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path) {
                 st = c->main.direct(c, dseed, dkey, n, ms[q], douts, true, &ps);
                 if (st == PA_OK && hipStreamSynchronize(c->main.stream) != hipSuccess) st = PA_EDEVICE;
                 c->main.timer.collect(ps.ms_pass);
-                if (r > 0 && ps.ms_pass[0] > 0) t[q] = std::min(t[q], ps.ms_pass[0] * 1e-3);
+                const double ms = ps.ms_pass[0] + ps.ms_pass[1];   // prep and product kernels
+                if (r > 0 && ms > 0) t[q] = std::min(t[q], ms * 1e-3);
             }
         if (st != PA_OK) {
             buf.release(c);

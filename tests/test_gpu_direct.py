@@ -112,7 +112,7 @@ def test_direct_timing_and_async(pa, ctx):
     s, k, o, n, m = _dev_job(p)
     assert pa.pa_hash(ctx, s, n, m, k, o, pa.PA_PREC_DIRECT | pa.PA_TIMING) == pa.PA_OK
     st = pa.pa_last_stats(ctx)
-    assert st["ms_pass"][0] > 0 and st["launches"] >= 2, st
+    assert st["ms_pass"][0] > 0 and st["ms_pass"][1] > 0 and st["launches"] >= 2, st
     o2 = torch.full_like(o, -1)
     torch.cuda.synchronize()   # the fill lands before the library's stream writes
     assert pa.pa_hash(ctx, s, n, m, k, o2, pa.PA_PREC_DIRECT | pa.PA_ASYNC) == pa.PA_OK
