@@ -135,8 +135,10 @@ typedef struct pa_stream pa_stream;
 /* Open a stream for an (n, m) job.  flags: the precision bits used for every
  * block (as for pa_hash) and PA_DEVICE_PTRS when the pointers given to
  * pa_stream_feed / _state / _resume / _close are device pointers.  The
- * accumulator starts at zero.  PA_EINVAL for n == 0, m == 0 or NULL;
- * PA_ENOMEM when the accumulator does not fit the context's budget. */
+ * accumulator starts at zero.  The stream uses the context (its stream and
+ * budget) and must be closed before the context is destroyed.  PA_EINVAL for
+ * n == 0, m == 0 or NULL; PA_ENOMEM when the accumulator does not fit the
+ * context's budget. */
 pa_status pa_stream_open(pa_ctx* ctx, uint64_t n, uint64_t m, uint32_t flags, pa_stream** stream);
 
 /* XOR the partial hash of key bits [lo, lo+len) into the accumulator.
