@@ -63,7 +63,7 @@ __device__ __forceinline__ TileGeo tile_geo(const JobDesc& jd, uint32_t lt) {
     g.dst = jd.out + (g.i0 >> 6);
     g.dst_words = (g.bo + 63) >> 6;
     g.accumulate = jd.nchunks > 1;
-    g.clears = g.accumulate && b == 0;
+    g.clears = g.accumulate && b == 0 && !jd.no_clear;
     return g;
 }
 

@@ -272,6 +272,9 @@ template <typename T> struct RowSmem {
     cx<T> t8[kLds ? 7 * 1024 : 1];
 };
 
+// Thread tid writes t8 entries e = tid (mod 512) and the forward transform's
+// thread tid reads only such entries (nb = tid + 512 s), so the first unit
+// needs no barrier after this load; the stage tables are first read after one.
 template <typename T>
 __device__ __forceinline__ void row_smem_load(RowSmem<T>& S, const cx<T>* __restrict__ tw,
                                               const cx<T>* __restrict__ stw, int tid) {

@@ -382,47 +382,79 @@ pa_status Lane::finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_s
             for (uint32_t t : failed) (*per_job)[job_of(t)] = PA_EPRECISION;
         return PA_EPRECISION;
     }
-    // Re-run in FP64 with the same geometry and length class: a failed tile of
-    // a one-chunk job alone (its window is overwritten); every tile of a job
-    // that accumulates chunks (its windows are cleared and rebuilt).
-    Tables tb;
+    // Re-run in FP64 with the same geometry and length class.
+    //  * One-chunk job: the failed tile alone (its window is overwritten).
+    //  * Job that accumulates chunks (Eq. 7): per failed tile, the FP32 tile
+    //    again and then the FP64 tile, both XOR-ing into the window without
+    //    clearing it; the FP32 run is deterministic, so its bits cancel the
+    //    first run's.  If the repeat's certificate is not bit-identical to the
+    //    first run's, the whole job is rebuilt in FP64 instead (its windows
+    //    cleared and rebuilt).
+    const ClassKernels* K32 = class_kernels(PREC_FP32, logL);
+    Tables tb, tb32;
     pa_status st = c->tables(PREC_FP64, logL, &tb);
+    if (st == PA_OK) st = c->tables(PREC_FP32, logL, &tb32);
     if (st != PA_OK) return st;
     st = ws.ensure(c, ((size_t)1 << logL) * 16);
     if (st != PA_OK) return st;
-    st = part.ensure(c, (size_t)(K64->cfg.n1 / K64->cfg.b1) * sizeof(uint32_t));
+    const size_t part_words = std::max<size_t>(K64->cfg.n1 / K64->cfg.b1, K32 ? K32->cfg.n1 / K32->cfg.b1 : 0);
+    st = part.ensure(c, part_words * sizeof(uint32_t));
     if (st != PA_OK) return st;
-    std::vector<uint8_t> whole(jobs.size(), 0);
-    std::vector<std::pair<size_t, uint32_t>> runs;   // (job, local tile); local = ~0u: all tiles
+    // (job, local tile, mode): 0 one-chunk tile, 1 accumulated tile, 2 whole job
+    struct Run { size_t job; uint32_t tile; int mode; };
+    std::vector<Run> runs;
     for (uint32_t t : failed) {
         const size_t jx = job_of(t);
-        if (jobs[jx].nchunks > 1) {
-            if (!whole[jx]) runs.push_back({jx, ~0u});
-            whole[jx] = 1;
-        } else {
-            runs.push_back({jx, t - jobs[jx].tile_begin});
-        }
+        runs.push_back({jx, t - jobs[jx].tile_begin, jobs[jx].nchunks > 1 ? 1 : 0});
     }
+    std::vector<uint8_t> rebuilt(jobs.size(), 0);
+    auto fetch_meta = [&](uint32_t first, uint32_t end, std::vector<TileMeta>* out) -> pa_status {
+        out->resize(end - first);
+        if (hipMemcpyAsync(out->data(), (TileMeta*)meta.ptr + first, (end - first) * sizeof(TileMeta),
+                           hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return PA_EDEVICE;
+        return PA_OK;
+    };
     pa_status result = PA_OK;
-    for (const auto& r : runs) {
-        const size_t jx = r.first;
+    for (size_t q = 0; q < runs.size(); ++q) {
+        Run r = runs[q];
+        const size_t jx = r.job;
+        if (rebuilt[jx]) continue;
         const uint32_t ntiles = jobs[jx].nchunks * jobs[jx].nouts;
-        const uint32_t first = r.second == ~0u ? 0u : r.second, end = r.second == ~0u ? ntiles : r.second + 1;
         JobTable jt{};
         jt.one = jobs[jx];
         jt.one.tile_begin = 0;
         jt.njobs = 0;
-        st = meta.ensure(c, (size_t)end * sizeof(TileMeta));
+        st = meta.ensure(c, (size_t)ntiles * sizeof(TileMeta));
         if (st != PA_OK) return st;
+        if (r.mode == 1) {
+            jt.one.no_clear = 1;
+            bool same = K32 != nullptr;
+            if (same) {
+                st = run_passes(K32, jt, r.tile, r.tile + 1, 1, this, tb32, false, &stats->launches);
+                if (st != PA_OK) return st;
+                std::vector<TileMeta> again;
+                st = fetch_meta(r.tile, r.tile + 1, &again);
+                if (st != PA_OK) return st;
+                const TileMeta& o = mt[jobs[jx].tile_begin + r.tile];
+                same = memcmp(&again[0], &o, sizeof(TileMeta)) == 0;
+                stats->tiles += 1;
+            }
+            if (!same) {   // rebuild the whole job
+                r.mode = 2;
+                jt.one.no_clear = 0;
+                rebuilt[jx] = 1;
+            }
+        }
+        const uint32_t first = r.mode == 2 ? 0u : r.tile, end = r.mode == 2 ? ntiles : r.tile + 1;
         st = run_passes(K64, jt, first, end, 1, this, tb, false, &stats->launches);
         if (st != PA_OK) return st;
         stats->fallback_tiles += end - first;
         stats->tiles += end - first;
-        std::vector<TileMeta> m64(end - first);
-        if (hipMemcpyAsync(m64.data(), (TileMeta*)meta.ptr + first, (end - first) * sizeof(TileMeta),
-                           hipMemcpyDeviceToHost, stream) != hipSuccess ||
-            hipStreamSynchronize(stream) != hipSuccess)
-            return PA_EDEVICE;
+        std::vector<TileMeta> m64;
+        st = fetch_meta(first, end, &m64);
+        if (st != PA_OK) return st;
         for (const TileMeta& m : m64) {
             double rr, aa;
             if (!tile_ok(PREC_FP64, m, &rr, &aa)) {

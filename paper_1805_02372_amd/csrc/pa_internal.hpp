@@ -25,6 +25,8 @@ struct JobDesc {
     uint32_t nchunks, nouts;
     uint32_t tile_begin;  // first tile of this job in the launch's tile numbering
     uint32_t out_words;   // ceil(m / 64)
+    uint32_t no_clear;    // 1: chunk-0 tiles do not clear their window (a tile
+                          // re-run that XORs into an accumulated window)
 };
 
 // Where the tiles of one launch come from: either one job passed by value or

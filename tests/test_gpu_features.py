@@ -130,8 +130,9 @@ def test_fallback_rebuilds_accumulated_job(pa, ctx, monkeypatch):
     """With the class capped at 2^21 the job is cut into key chunks whose
     partial hashes are XOR-accumulated.  With an all-ones key and seed every
     window value equals the chunk length (> 2^20), so every FP32 tile fails
-    its certificate and the whole job is rebuilt in FP64.  Closed form: every
-    output is n mod 2.  A random job in the same batch keeps its FP32 result."""
+    its certificate; each is replaced in place (its FP32 bits XOR-ed out by a
+    repeat, the FP64 tile's XOR-ed in).  Closed form: every output is n mod 2.
+    A random job in the same batch keeps its FP32 result."""
     from gpu_util import to_dev, from_dev, empty_dev
     monkeypatch.setenv("PA_MAX_LOG2_LEN", "21")
     rng = np.random.default_rng(22)
