@@ -231,6 +231,22 @@ def run_serving(pa, chk_ctx, torch, count: int, load: float = 0.7, budget_gib: i
     return main
 
 
+def run_host_pointers(pa, ctx, prob, steps: int = 10):
+    """The c3 job from host memory (numpy arrays): each call copies seed and key
+    to the device and the output back, over PCIe.  Reported beside the
+    resident-input rate, never as the headline."""
+    out = np.zeros((prob.m + 63) // 64, np.uint64)
+    for _ in range(2):
+        assert pa.pa_hash(ctx, prob.seed, prob.n, prob.m, prob.key, out, pa.PA_PREC_AUTO) == pa.PA_OK
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        assert pa.pa_hash(ctx, prob.seed, prob.n, prob.m, prob.key, out, pa.PA_PREC_AUTO) == pa.PA_OK
+    el = (time.perf_counter() - t0) / steps
+    return {"gbps_including_copies": round(prob.n / el / 1e9, 3), "ms_per_call": round(el * 1e3, 4),
+            "bytes_copied": int(((prob.n + prob.m - 1 + 63) // 64 + (prob.n + 63) // 64 + (prob.m + 63) // 64) * 8),
+            "out": out}
+
+
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 
 
@@ -370,6 +386,7 @@ def main():
     ap.add_argument("--no-direct", action="store_true", help="skip the direct-path (short output) leg")
     ap.add_argument("--no-table1", action="store_true", help="skip the 4-128 Mbit sweep")
     ap.add_argument("--no-stream", action="store_true", help="skip the block-serial host streaming leg")
+    ap.add_argument("--no-host", action="store_true", help="skip the c3 leg from host memory (PCIe copies)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 512 MiB device copy (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -401,6 +418,12 @@ def main():
         res[name] = r
         log(f"[bench] c3 {name}: {prob.n * args.steps / r['elapsed'] / 1e9:.2f} Gbps, bit-exact={ok}, "
             f"kernel ms {r['kernel_ms']}")
+
+    host = None
+    if not args.only and not args.no_host:
+        host = run_host_pointers(pa, ctx, prob)
+        host["bit_exact"] = hashlib.sha256(host.pop("out").astype("<u8").tobytes()).hexdigest() == golden["c3"]["sha256"]
+        log(f"[bench] c3 from host memory: {host}")
 
     batch = None
     if not args.no_batch and not args.only:
@@ -518,6 +541,8 @@ def main():
         line["batch_c4"] = {"jobs": 64, "gbps": round(batch["gbps"], 3), "tiles": batch["stats"]["tiles"],
                             "log2_len": batch["stats"]["log2_len"], "bit_exact": bool(batch["bit_exact"]),
                             "fallback_tiles": batch["stats"]["fallback_tiles"]}
+    if host is not None:
+        line["c3_host_pointers"] = host
     if batch is not None:
         line["batch_c4"]["direct_jobs"] = batch["stats"]["direct_jobs"]
     if direct is not None:
