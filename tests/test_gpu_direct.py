@@ -183,6 +183,8 @@ def test_select_rejects_bad_input(pa, ctx):
     assert st == pa.PA_EINVAL
     st, bits = pa.pa_hash_select(ctx, p.seed, 100, 10, p.key, [])
     assert st == pa.PA_OK and bits.size == 0
+    st, _ = pa.pa_hash_select(ctx, p.seed, 100, 10, p.key, np.zeros((1 << 20) + 1, np.uint64))
+    assert st == pa.PA_EINVAL   # more than 2^20 indices
 
 
 def test_tune_measures_direct_cost(pa, tmp_path):
