@@ -26,7 +26,7 @@ What fixes each check:
 * ``pin_linearity``: T(x xor z) = Tx xor Tz.
 * ``pin_block_split``: paper Eq. 4-7 (split the key into blocks, hash each
   block with its slice of T, XOR the intermediate keys) and the output split
-  (the matrix columns "may also need to be divided", section 3).
+  (section 3 allows splitting the matrix columns as well).
 * ``pin_universal``: every nonzero difference d is mapped to 0 by exactly
   2^(n-1) of the 2^(n+m-1) seeds (collision probability exactly 2^-m for the
   full Toeplitz family; section 2.1 quotes a looser n*2^(-m+1)).
