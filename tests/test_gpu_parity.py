@@ -191,3 +191,36 @@ def test_random_shapes_every_path(pa, ctx, n, m):
         st, y = _run(pa, ctx, p, flags)
         assert st == pa.PA_OK, (prec, pa.pa_strerror(st))
         assert np.array_equal(y, ref), f"{prec}: " + describe(y, ref, m)
+
+
+GUARD = 8
+SENTINEL = np.uint64(0xA5A5A5A5A5A5A5A5)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "ntt", "direct", "auto"])
+@pytest.mark.parametrize("n,m", [(70_000, 9_001), (3_000_001, 300_007), (5, 64), (200_003, 1)])
+def test_guard_words_untouched(pa, ctx, prec, n, m):
+    """The output's ceil(m/64) words are written (bits past m as 0) and the
+    guard words after them are never touched, on every path, including key
+    chunks XOR-accumulated under a capped class (2^20)."""
+    import torch
+    from gpu_util import to_dev, from_dev
+    flags = pa.PA_PREC_DIRECT if prec == "direct" else _flags(pa, prec)
+    rng = np.random.default_rng(n + 7 * m)
+    p = synth.random_problem(rng, n, m)
+    w = synth.words_for(m)
+    out = to_dev(np.full(w + GUARD, SENTINEL, np.uint64))
+    old = os.environ.get("PA_MAX_LOG2_LEN")
+    os.environ["PA_MAX_LOG2_LEN"] = "20"
+    try:
+        st = pa.pa_hash(ctx, to_dev(p.seed), n, m, to_dev(p.key), out, flags)
+        torch.cuda.synchronize()
+    finally:
+        if old is None:
+            del os.environ["PA_MAX_LOG2_LEN"]
+        else:
+            os.environ["PA_MAX_LOG2_LEN"] = old
+    assert st == pa.PA_OK, pa.pa_strerror(st)
+    y = from_dev(out)
+    assert np.array_equal(y[:w], oracle.hash_words(p.seed, n, m, p.key))
+    assert np.all(y[w:] == SENTINEL), "guard words written"
