@@ -64,7 +64,8 @@ typedef enum {
 #define PA_PREC_MASK      0x00F0u
 #define PA_NO_FALLBACK    0x0100u  /* report PA_EPRECISION instead of re-running FP64   */
 #define PA_ASYNC          0x0200u  /* with PA_DEVICE_PTRS and an exact or a-priori
-                                      certified plan (FP64, NTT): return once enqueued  */
+                                      certified plan (FP64, NTT, direct): return once
+                                      enqueued                                          */
 #define PA_TIMING         0x0400u  /* record per-kernel durations (pa_last_stats)       */
 
 typedef struct pa_ctx pa_ctx;
