@@ -81,9 +81,10 @@ void pa_destroy(pa_ctx* ctx);
 /* y = T(seed) * key over GF(2), m output bits (see top of file).
  * seed: n+m-1 bits; key: n bits; out: m bits (ceil(m/64) words, written).
  * Synchronous unless PA_ASYNC applies.  PA_EINVAL for n == 0, m == 0, NULL
- * pointers or an unknown precision; PA_ENOMEM when even the smallest tiling
- * exceeds the budget; PA_EPRECISION when a certificate fails and
- * PA_NO_FALLBACK is set. */
+ * pointers, an unknown precision, n or m above 2^40, or m above 2^38 (a plan
+ * has at most 2^14 output windows of at most 2^24 bits); PA_ENOMEM when even
+ * the smallest tiling exceeds the budget; PA_EPRECISION when a certificate
+ * fails and PA_NO_FALLBACK is set. */
 pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m,
                   const uint64_t* key, uint64_t* out, uint32_t flags);
 

@@ -175,6 +175,18 @@ def test_direct_path_choice(pa):
     assert pa.pa_error_model(pa.PA_PREC_DIRECT, 20, 1000) == 0.0
 
 
+def test_size_limits(pa):
+    """Plans exist up to n = 2^40 (key chunks) and m = 2^38 (2^14 windows of
+    2^24 bits); longer outputs are rejected, not mis-planned."""
+    for f in (pa.PA_PREC_AUTO, pa.PA_PREC_FP64, pa.PA_PREC_NTT):
+        p = pa.pa_plan_query(1 << 40, 1, f)
+        assert p["chunks"] * p["chunk_bits"] >= 1 << 40
+        p = pa.pa_plan_query(5, 1 << 38, f)
+        assert p["windows"] <= 1 << 14 and p["windows"] * p["window_bits"] >= 1 << 38
+        with pytest.raises(pa.PAError):
+            pa.pa_plan_query(5, (1 << 38) + (1 << 24), f)
+
+
 def test_plan_query_rejects_bad_input(pa):
     with pytest.raises(pa.PAError):
         pa.pa_plan_query(0, 5, 0)
