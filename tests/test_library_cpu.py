@@ -96,6 +96,30 @@ def test_plan_covers_every_pair_once(pa, n, m, prec):
         assert bi >= 1 and bo >= 1 and bi + bo - 1 <= L
 
 
+def test_plan_invariants_random_shapes(pa):
+    """Property check over random shapes (hypothesis, a fixed number of cases):
+    every plan's chunks tile the key and its windows tile the output once, no
+    tile wraps (Bi + Bo - 1 <= L), window starts are word aligned, and FP plans
+    respect the error limit."""
+    hyp = pytest.importorskip("hypothesis")
+    st = hyp.strategies
+
+    @hyp.settings(max_examples=300, deadline=None, derandomize=True)
+    @hyp.given(n=st.integers(1, 1 << 34), m=st.integers(1, 1 << 30),
+               f=st.sampled_from([pa.PA_PREC_AUTO, pa.PA_PREC_FP64, pa.PA_PREC_NTT]))
+    def check(n, m, f):
+        p = pa.pa_plan_query(n, m, f)
+        L = 1 << p["log2_len"]
+        Bi, Bo, C, W = p["chunk_bits"], p["window_bits"], p["chunks"], p["windows"]
+        assert Bi + Bo - 1 <= L
+        assert C == -(-n // Bi) and W == -(-m // Bo) and (C - 1) * Bi < n and (W - 1) * Bo < m
+        assert W == 1 or Bo % 64 == 0
+        if f != pa.PA_PREC_NTT:
+            assert p["bound"] <= 0.25
+
+    check()
+
+
 def test_tile_geometry_reproduces_the_hash():
     """The documented tile geometry (seed slice per tile, Eq. 4-7 XOR of key
     chunks, output windows) recomputes the definition exactly; checked with the
