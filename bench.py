@@ -107,6 +107,48 @@ def run_single(pa, ctx, torch, prob, flags, steps, warmup):
     return dict(elapsed=el, lat=np.array(lat), stats=stats, kernel_ms=kms.tolist(), out=out)
 
 
+def run_latency_c1(pa, ctx, torch, calls: int = 200, warmup: int = 20):
+    """c1 (n = 131,072, m = 16,384) on the plain FP64 path: a latency-bound
+    single hash.  Per-call wall time (launches, kernels, certificate read-back)
+    over `calls` synchronous calls, inputs resident in HBM."""
+    import synth
+    prob = synth.single_config("c1")
+    r = run_single(pa, ctx, torch, prob, pa.PA_PREC_FP64, calls, warmup)
+    st = r["stats"]
+    return prob, {"n": prob.n, "m": prob.m, "path": "fp64_plain",
+                  "p50_us": round(float(np.percentile(r["lat"], 50)) * 1e6, 1),
+                  "p99_us": round(float(np.percentile(r["lat"], 99)) * 1e6, 1),
+                  "mean_us": round(r["elapsed"] / calls * 1e6, 1),
+                  "kernel_us": [round(x * 1e3, 2) for x in r["kernel_ms"][:3]],
+                  "gbps": round(prob.n * calls / r["elapsed"] / 1e9, 3),
+                  "log2_len": st["log2_len"], "tiles": st["tiles"],
+                  "rigorous_bound": st["rigorous_bound"], "certified": CERT_NAMES[st["certified"]],
+                  "out": r["out"]}
+
+
+def run_c2(pa, ctx, torch, steps, warmup):
+    """c2 (n = 10^6, m = 2 * 10^5): the FP64 full-length single tile against
+    the FP32 segmented plan, with each plan's length, chunk, window, model
+    bound and worst-case bound."""
+    import synth
+    prob = synth.single_config("c2")
+    out = {"n": prob.n, "m": prob.m}
+    outs = {}
+    for name, flags in (("fp64_plain", pa.PA_PREC_FP64), ("fp32_segmented", pa.PA_PREC_FP32_SEG)):
+        r = run_single(pa, ctx, torch, prob, flags, steps, warmup)
+        st = r["stats"]
+        out[name] = {"gbps": round(prob.n * steps / r["elapsed"] / 1e9, 3),
+                     "ms_per_call": round(r["elapsed"] / steps * 1e3, 4),
+                     "p99_ms": round(float(np.percentile(r["lat"], 99)) * 1e3, 4),
+                     "kernel_ms": [round(x, 5) for x in r["kernel_ms"][:3]],
+                     "log2_len": st["log2_len"], "chunk_bits": st["chunk_bits"], "window_bits": st["window_bits"],
+                     "tiles": st["tiles"], "model_bound": st["bound"], "rigorous_bound": st["rigorous_bound"],
+                     "max_residual": st["max_residual"], "fallback_tiles": st["fallback_tiles"],
+                     "certified": CERT_NAMES[st["certified"]]}
+        outs[name] = r["out"]
+    return prob, out, outs
+
+
 def run_batch(pa, ctx, torch, jobs, flags, steps, warmup):
     dev = []
     for p in jobs:
@@ -197,7 +239,9 @@ def run_serving(pa, chk_ctx, torch, count: int, load: float = 0.7, budget_gib: i
         main = play(ctx, sids, list(range(count)), load * cap / mean_n)
         ss = pa.pa_serve_stats(ctx)
         main.update({"load": load, "hbm_budget_gib": budget_gib, "burst_capacity_gbps": round(cap / 1e9, 3),
-                     "tiles": ss["tiles"], "fallback_tiles": ss["fallback_tiles"]})
+                     "tiles": ss["tiles"], "fallback_tiles": ss["fallback_tiles"],
+                     "fallback_rate": round(ss["fallback_tiles"] / max(1, ss["tiles"]), 6),
+                     "direct_jobs": ss["direct_jobs"]})
         sub = list(range(min(500, count)))
         sweep = []
         for lf in (0.5, 0.9):
@@ -247,6 +291,7 @@ def run_host_pointers(pa, ctx, prob, steps: int = 10):
             "out": out}
 
 
+CERT_NAMES = {0: "none", 1: "exact", 2: "a-priori", 3: "a-posteriori"}
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 
 
@@ -345,7 +390,7 @@ def run_stream_leg(pa, ctx, torch, n: int = 128_000_000, m: int = 1_000_000, blo
             "spot_check_exact": bool(np.array_equal(ref, synth.bits_to_array(out, m)[idx]))}
 
 
-def cpu_baseline(prob, target_s: float = 12.0, whole_s: float = 30.0):
+def cpu_baseline(prob, target_s: float = 12.0, whole_s: float = 30.0, extra=None):
     """Oracle on a prefix of the outputs (full key): by the constant diagonals
     y[0:m'] is the hash with seed bits [0, n+m'-1) and m' outputs; its cost is
     linear in m', so the full job's time is t * m / m'.  When the whole job is
@@ -367,7 +412,14 @@ def cpu_baseline(prob, target_s: float = 12.0, whole_s: float = 30.0):
             break
         m_try = min(prob.m, int(m_try * min(8.0, max(2.0, target_s / max(t, 1e-3)))))
     full = t * prob.m / m_try
+    others = {}
+    for name, q in (extra or {}).items():   # small whole jobs (c1, c2), timed in full
+        a = time.perf_counter()
+        oracle.hash_words(q.seed, q.n, q.m, q.key, threads=threads)
+        dt = time.perf_counter() - a
+        others[name] = {"seconds": round(dt, 4), "gbps": round(q.n / dt / 1e9, 6), "n": q.n, "m": q.m}
     return {"value": prob.n / full / 1e9, "unit": "Gbps", "cores": threads, "kind": "oracle",
+            "other_configs": others,
             "sample": (f"word-parallel oracle on the whole job ({prob.m} outputs, full key), {t:.2f} s"
                        if m_try >= prob.m else
                        f"word-parallel oracle on outputs [0, {m_try}) of {prob.m} (full key), "
@@ -387,6 +439,7 @@ def main():
     ap.add_argument("--no-table1", action="store_true", help="skip the 4-128 Mbit sweep")
     ap.add_argument("--no-stream", action="store_true", help="skip the block-serial host streaming leg")
     ap.add_argument("--no-host", action="store_true", help="skip the c3 leg from host memory (PCIe copies)")
+    ap.add_argument("--no-small", action="store_true", help="skip the c1 latency and c2 precision legs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 512 MiB device copy (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -425,12 +478,33 @@ def main():
         host["bit_exact"] = hashlib.sha256(host.pop("out").astype("<u8").tobytes()).hexdigest() == golden["c3"]["sha256"]
         log(f"[bench] c3 from host memory: {host}")
 
+    c1 = c2 = None
+    c1_prob = c2_prob = None
+    if not args.only and not args.no_small:
+        c1_prob, c1 = run_latency_c1(pa, ctx, torch)
+        c1["bit_exact"] = hashlib.sha256(c1.pop("out").astype("<u8").tobytes()).hexdigest() == golden["c1"]["sha256"]
+        log(f"[bench] c1 latency: {c1}")
+        c2_prob, c2, c2_outs = run_c2(pa, ctx, torch, args.steps, args.warmup)
+        for name, o in c2_outs.items():
+            c2[name]["bit_exact"] = hashlib.sha256(o.astype("<u8").tobytes()).hexdigest() == golden["c2"]["sha256"]
+        log(f"[bench] c2: {c2}")
+
     batch = None
     if not args.no_batch and not args.only:
         jobs = synth.batch_jobs()
         log(f"[bench] c4 batch of {len(jobs)} jobs")
         bsteps = max(2, args.steps // 4)
-        batch = run_batch(pa, ctx, torch, jobs, pa.PA_PREC_AUTO, bsteps, max(1, args.warmup // 2))
+        # segment sizes from the tuner: a context of its own measures the class
+        # costs first (the headline context keeps the built-in model)
+        bctx = pa.pa_create(0, 0, None)
+        a = time.perf_counter()
+        assert pa.pa_tune(bctx, pa.PA_PREC_AUTO, 3) == pa.PA_OK
+        tune_s = time.perf_counter() - a
+        try:
+            batch = run_batch(pa, bctx, torch, jobs, pa.PA_PREC_AUTO, bsteps, max(1, args.warmup // 2))
+        finally:
+            pa.pa_destroy(bctx)
+        batch["tune_s"] = tune_s
         g = golden.get("c4", [])
         bexact = len(g) == len(jobs) and all(
             hashlib.sha256(o.astype("<u8").tobytes()).hexdigest() == gg["sha256"]
@@ -526,7 +600,14 @@ def main():
         "bit_exact": bool(head["bit_exact"]),
         "max_residual": st["max_residual"],
         "fallback_tiles": st["fallback_tiles"],
+        "precision": {"certified": CERT_NAMES[st["certified"]], "model_bound": st["bound"],
+                      "rigorous_bound": st["rigorous_bound"], "max_residual": st["max_residual"],
+                      "fallback_tiles": st["fallback_tiles"], "tiles": st["tiles"]},
     }
+    if c1 is not None:
+        line["c1_latency"] = c1
+    if c2 is not None:
+        line["c2_precision"] = c2
     if "fp64" in res and head_name != "fp64":
         r = res["fp64"]
         line["fp64_plain"] = {
@@ -540,7 +621,10 @@ def main():
     if batch is not None:
         line["batch_c4"] = {"jobs": 64, "gbps": round(batch["gbps"], 3), "tiles": batch["stats"]["tiles"],
                             "log2_len": batch["stats"]["log2_len"], "bit_exact": bool(batch["bit_exact"]),
-                            "fallback_tiles": batch["stats"]["fallback_tiles"]}
+                            "fallback_tiles": batch["stats"]["fallback_tiles"],
+                            "launches_per_batch": batch["stats"]["launches"],
+                            "tuned": True, "tune_s": round(batch["tune_s"], 3),
+                            "certified": CERT_NAMES[batch["stats"]["certified"]]}
     if host is not None:
         line["c3_host_pointers"] = host
     if batch is not None:
@@ -555,7 +639,8 @@ def main():
         line["serving_c5"] = serving
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(prob)
+        extra = {k: v for k, v in (("c1", c1_prob), ("c2", c2_prob)) if v is not None}
+        line["cpu_baseline"] = cpu_baseline(prob, extra=extra)
     pa.pa_destroy(ctx)
     print(json.dumps(line), flush=True)
 

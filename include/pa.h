@@ -164,7 +164,11 @@ pa_status pa_stream_resume(pa_stream* stream, const uint64_t* acc, uint64_t fed_
  * were fed.  The stream is freed in every case. */
 pa_status pa_stream_close(pa_stream* stream, uint64_t* out);
 
-/* ---- serving (continuous batching) --------------------------------------- */
+/* ---- serving (continuous batching) ---------------------------------------
+ * The paper has no serving passage; it motivates real-time hashing of keys
+ * that are already resident on the GPU (section 3).  Requests are hashed
+ * exactly as pa_hash with PA_PREC_AUTO would hash them: short outputs by the
+ * direct product, the rest by FP32 tiles with FP64 fallback. */
 
 /* Copy a seed of nbits bits (device pointer if PA_DEVICE_PTRS in flags, else
  * host) into library-owned device memory and return its id.  Requests that
@@ -190,7 +194,25 @@ pa_status pa_wait(pa_ctx* ctx, uint64_t ticket);
 /* Latency of a finished ticket in seconds (submit -> completion seen). */
 pa_status pa_ticket_latency(pa_ctx* ctx, uint64_t ticket, double* seconds);
 
+/* Forget a finished ticket: its record (status, latency) is freed and the
+ * ticket becomes unknown to pa_poll / pa_wait / pa_ticket_latency.  A
+ * long-running service releases every ticket once it has read it; records of
+ * unreleased tickets live until pa_destroy (pa_serve_stats counts them).
+ * PA_ENOTREADY while the ticket runs, PA_EINVAL for an unknown ticket. */
+pa_status pa_ticket_release(pa_ctx* ctx, uint64_t ticket);
+
 /* ---- statistics ----------------------------------------------------------- */
+
+/* How a result is known to be exact (pa_stats.certified). */
+#define PA_CERT_NONE          0u  /* no result (error, or nothing ran)              */
+#define PA_CERT_EXACT         1u  /* integer arithmetic only (NTT, direct product)   */
+#define PA_CERT_A_PRIORI      2u  /* every floating-point tile is within the worst-case
+                                     rounding bound (rigorous_bound < 0.5): rigorously
+                                     certified for any input bits                     */
+#define PA_CERT_A_POSTERIORI  3u  /* some FP32 tile is not covered by the worst-case
+                                     bound; each such tile passed its run-time check
+                                     (max |z - rint z| <= 1/8, |z| < 2^20, even
+                                     rint z + weight, finite) or was re-run in FP64   */
 
 typedef struct {
     uint32_t prec;            /* PA_PREC_* of the plan that ran               */
@@ -211,6 +233,12 @@ typedef struct {
     uint64_t launches;        /* kernel launches                              */
     uint64_t direct_jobs;     /* jobs that ran on the direct path (prec is
                                  PA_PREC_DIRECT when all of them did)         */
+    double rigorous_bound;    /* worst-case error bound of the FP plan (for any
+                                 input bits); 0 for exact paths              */
+    uint32_t certified;       /* how the result is known exact: PA_CERT_*     */
+    uint32_t reserved;
+    uint64_t live_requests;   /* pa_serve_stats: request records held (queued,
+                                 running, or finished and not yet released)  */
 } pa_stats;
 
 /* Statistics of the last pa_hash / pa_hash_batch on this context. */
@@ -262,6 +290,9 @@ typedef struct {
     uint32_t direct;      /* 1: the flags run (n, m) on the direct path; the
                              fields above still describe the FFT plan   */
     uint32_t reserved;
+    double rigorous_bound; /* worst-case rounding bound of one tile of the plan,
+                              for any input bits (0 for NTT); below 0.5 the plan
+                              is certified a priori                      */
 } pa_plan;
 
 /* The plan pa_hash would use for (n, m) under the precision bits of flags,

@@ -329,7 +329,8 @@ k_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta, 
                 const T r = round_even(z);
                 const int64_t s2 = (int64_t)r + weight;      // = 2c when exact
                 bit = (uint32_t)(s2 >> 1) & 1u;
-                bad += (uint32_t)(s2 & 1);
+                // an odd sum, or a non-finite z (fmaxf would drop a NaN)
+                bad += (uint32_t)(s2 & 1) + (fabs(z - r) <= T(0.5) ? 0u : 1u);
                 mres = fmaxf(mres, (float)fabs(z - r));
                 mabs = fmaxf(mabs, (float)fabs(z));
             }

@@ -624,7 +624,8 @@ k2_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta,
             const T zz = e ? v[i].im : v[i].re;
             const T r = round_even(zz);
             const uint32_t s2 = low2(r) + wlow;
-            bad += (valid && (s2 & 1u)) ? 1u : 0u;
+            // an odd sum, or a non-finite z (fmaxf below would drop a NaN)
+            bad += (valid && ((s2 & 1u) || !(fabs(zz - r) <= T(0.5)))) ? 1u : 0u;
             mres = fmaxf(mres, valid ? (float)fabs(zz - r) : 0.f);
             mabs = fmaxf(mabs, valid ? (float)fabs(zz) : 0.f);
             mybits |= (valid ? ((s2 >> 1) & 1u) : 0u) << (2 * i + e);

@@ -40,7 +40,7 @@ static uint64_t words_of(uint64_t bits) { return (bits + 63) >> 6; }
 
 // ------------------------------------------------------------ device memory
 
-pa_status DevBuf::ensure(Ctx* c, size_t need) {
+pa_status DevBuf::ensure(Ctx* c, size_t need, hipStream_t stream) {
     if (need <= bytes) return PA_OK;
     release(c);
     size_t want = std::max(need, (size_t)256);
@@ -48,8 +48,11 @@ pa_status DevBuf::ensure(Ctx* c, size_t need) {
     do {  // reserve against the budget
         if (cur + want > c->budget) return PA_ENOMEM;
     } while (!c->used.compare_exchange_weak(cur, cur + want));
-    if (hipMalloc(&ptr, want) != hipSuccess) {
+    owner = c->pools ? stream : nullptr;
+    const hipError_t e = owner ? hipMallocAsync(&ptr, want, owner) : hipMalloc(&ptr, want);
+    if (e != hipSuccess) {
         ptr = nullptr;
+        owner = nullptr;
         c->used -= want;
         (void)hipGetLastError();
         return PA_ENOMEM;
@@ -60,12 +63,17 @@ pa_status DevBuf::ensure(Ctx* c, size_t need) {
 
 void DevBuf::release(Ctx* c) {
     if (ptr) {
-        (void)hipDeviceSynchronize();  // no launch may still use it
-        (void)hipFree(ptr);
+        if (owner) {
+            (void)hipFreeAsync(ptr, owner);   // after the owner's queued work
+        } else {
+            (void)hipDeviceSynchronize();     // no launch may still use it
+            (void)hipFree(ptr);
+        }
         c->used -= bytes;
     }
     ptr = nullptr;
     bytes = 0;
+    owner = nullptr;
 }
 
 pa_status HostBuf::ensure(size_t need) {
@@ -220,13 +228,13 @@ void fill_job(JobDesc* jd, const uint64_t* seed, const uint64_t* key, uint64_t* 
 }
 
 void Lane::release(Ctx* c) {
-    if (stream) (void)hipStreamSynchronize(stream);
     ws.release(c);
     part.release(c);
     meta.release(c);
     jobs_dev.release(c);
     io.release(c);
     aux.release(c);
+    if (stream) (void)hipStreamSynchronize(stream);   // the frees above are in its order
     meta_host.release();
     jobs_host.release();
     timer.destroy();
@@ -272,11 +280,11 @@ pa_status Lane::launch(Ctx* c, int prec_, int logL_, std::vector<JobDesc>& js, b
     Tables tb;
     pa_status st = c->tables(prec, logL, &tb);
     if (st != PA_OK) return st;
-    st = meta.ensure(c, (size_t)total * sizeof(TileMeta));
+    st = meta.ensure(c, (size_t)total * sizeof(TileMeta), stream);
     if (st != PA_OK) return st;
 
     if (js.size() > 1) {  // descriptors first: they are small but must fit
-        st = jobs_dev.ensure(c, js.size() * sizeof(JobDesc));
+        st = jobs_dev.ensure(c, js.size() * sizeof(JobDesc), stream);
         if (st != PA_OK) return st;
         st = jobs_host.ensure(js.size() * sizeof(JobDesc));
         if (st != PA_OK) return st;
@@ -295,8 +303,8 @@ pa_status Lane::launch(Ctx* c, int prec_, int logL_, std::vector<JobDesc>& js, b
         G = std::max<size_t>(1, std::min<size_t>(G, avail / (tile_bytes + part_bytes)));
     }
     for (;;) {
-        st = ws.ensure(c, G * tile_bytes);
-        if (st == PA_OK) st = part.ensure(c, G * part_bytes);
+        st = ws.ensure(c, G * tile_bytes, stream);
+        if (st == PA_OK) st = part.ensure(c, G * part_bytes, stream);
         if (st == PA_OK || G == 1) break;
         G = (G + 1) / 2;
     }
@@ -395,10 +403,10 @@ pa_status Lane::finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_s
     pa_status st = c->tables(PREC_FP64, logL, &tb);
     if (st == PA_OK) st = c->tables(PREC_FP32, logL, &tb32);
     if (st != PA_OK) return st;
-    st = ws.ensure(c, ((size_t)1 << logL) * 16);
+    st = ws.ensure(c, ((size_t)1 << logL) * 16, stream);
     if (st != PA_OK) return st;
     const size_t part_words = std::max<size_t>(K64->cfg.n1 / K64->cfg.b1, K32 ? K32->cfg.n1 / K32->cfg.b1 : 0);
-    st = part.ensure(c, part_words * sizeof(uint32_t));
+    st = part.ensure(c, part_words * sizeof(uint32_t), stream);
     if (st != PA_OK) return st;
     // (job, local tile, mode): 0 one-chunk tile, 1 accumulated tile, 2 whole job
     struct Run { size_t job; uint32_t tile; int mode; };
@@ -426,7 +434,7 @@ pa_status Lane::finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_s
         jt.one = jobs[jx];
         jt.one.tile_begin = 0;
         jt.njobs = 0;
-        st = meta.ensure(c, (size_t)ntiles * sizeof(TileMeta));
+        st = meta.ensure(c, (size_t)ntiles * sizeof(TileMeta), stream);
         if (st != PA_OK) return st;
         if (r.mode == 1) {
             jt.one.no_clear = 1;
@@ -469,7 +477,7 @@ pa_status Lane::finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_s
 
 pa_status Lane::direct(Ctx* c, const uint64_t* seed, const uint64_t* key, uint64_t n, uint64_t m, uint64_t* out,
                        bool timing, pa_stats* stats) {
-    pa_status st = aux.ensure(c, direct_key_words(n) * 4);
+    pa_status st = aux.ensure(c, direct_key_words(n) * 4, stream);
     if (st != PA_OK) return st;
     // PA_TIMING: ms_pass[0] the prep kernel, ms_pass[1] the product kernels
     hipEvent_t a = timing ? timer.mark(stream) : nullptr;
@@ -510,7 +518,16 @@ void fill_plan_stats(pa_stats* s, const TilePlan& p) {
     s->chunk_bits = p.Bi;
     s->window_bits = p.Bo;
     s->bound = std::max(s->bound, p.bound);
+    s->rigorous_bound = std::max(s->rigorous_bound, p.rigorous);
+    if (p.prec == PREC_FP32 || p.prec == PREC_FP64) s->certified = PA_CERT_A_PRIORI;   // settled by set_certified
     s->model_bytes += p.tiles() * ((p.prec == PREC_FP64 ? 48ull : 24ull) << p.logL);
+}
+
+void set_certified(pa_stats* s, pa_status st) {
+    if (st != PA_OK) s->certified = PA_CERT_NONE;
+    else if (s->certified == PA_CERT_A_PRIORI && !(s->rigorous_bound < kRigorousLimit))
+        s->certified = PA_CERT_A_POSTERIORI;
+    else if (s->certified != PA_CERT_A_PRIORI) s->certified = PA_CERT_EXACT;
 }
 
 }  // namespace pa
@@ -532,6 +549,10 @@ pa_status pa_create(pa_ctx** out, int device, uint64_t budget, void* hip_stream)
     if (hipSetDevice(device) != hipSuccess) return PA_EDEVICE;
     Ctx* c = new Ctx();
     c->device = device;
+    int pools = 0;
+    c->pools = hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, device) == hipSuccess &&
+               pools != 0;
+    (void)hipGetLastError();
     c->budget = budget ? budget : (8ull << 30);
     if (hip_stream) {
         c->main.stream = (hipStream_t)hip_stream;
@@ -584,7 +605,7 @@ pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, con
     uint64_t* dout = out;
     const bool dev = flags & PA_DEVICE_PTRS;
     if (!dev) {  // stage host buffers through library memory
-        pa_status s = ln.io.ensure(c, (sw + kw + ow) * 8);
+        pa_status s = ln.io.ensure(c, (sw + kw + ow) * 8, ln.stream);
         if (s != PA_OK) return s;
         uint64_t* base = (uint64_t*)ln.io.ptr;
         if (hipMemcpyAsync(base, seed, sw * 8, hipMemcpyHostToDevice, ln.stream) != hipSuccess ||
@@ -615,9 +636,10 @@ pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, con
     } else {
         std::vector<JobDesc> jobs(1);
         fill_job(&jobs[0], dseed, dkey, dout, n, m, plan);
-        // Only an a-priori certified plan may skip the certificate read-back;
-        // kernel timing needs the launch to finish.
-        const bool async = dev && (flags & PA_ASYNC) && plan.prec != PREC_FP32 && !timing;
+        // Only an a-priori certified plan (worst-case bound below 0.5, or
+        // NTT) may skip the certificate read-back; kernel timing needs the
+        // launch to finish.
+        const bool async = dev && (flags & PA_ASYNC) && plan.rigorous < kRigorousLimit && !timing;
         s = ln.launch(c, plan.prec, plan.logL, jobs, timing, !async, &st);
         if (s == PA_OK && !async) s = ln.finish(c, flags, &st, nullptr);
     }
@@ -626,6 +648,7 @@ pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, con
             hipStreamSynchronize(ln.stream) != hipSuccess)
             s = PA_EDEVICE;
     }
+    set_certified(&st, s);
     c->last = st;
     return s;
 }
@@ -719,7 +742,7 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
         uint64_t total_words = 0;
         for (uint64_t i = 0; i < count; ++i)
             total_words += words_of(ns[i] + ms[i] - 1) + words_of(ns[i]) + words_of(ms[i]);
-        pa_status s = ln.io.ensure(c, total_words * 8);
+        pa_status s = ln.io.ensure(c, total_words * 8, ln.stream);
         if (s != PA_OK) return s;
     }
     uint64_t off = 0;
@@ -840,6 +863,7 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
     }
     if (per_job)
         for (uint64_t i = 0; i < count; ++i) per_job[i] = (s == PA_OK || s == PA_EPRECISION) ? status[i] : s;
+    set_certified(&st, s);
     c->last = st;
     return s;
 }
@@ -874,6 +898,7 @@ pa_status pa_plan_query(uint64_t n, uint64_t m, uint32_t flags, pa_plan* out) {
     out->direct_cost = direct_cost(n, m, cm);
     out->direct = choose_direct(flags, n, m, cm, p) ? 1u : 0u;
     out->reserved = 0;
+    out->rigorous_bound = p.rigorous;
     return PA_OK;
 }
 
@@ -891,7 +916,7 @@ pa_status pa_hash_select(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t
     const uint64_t *dseed = seed, *dkey = key;
     if (!(flags & PA_DEVICE_PTRS)) {
         const uint64_t sw = words_of(n + m - 1), kw = words_of(n);
-        pa_status s = ln.io.ensure(c, (sw + kw) * 8);
+        pa_status s = ln.io.ensure(c, (sw + kw) * 8, ln.stream);
         if (s != PA_OK) return s;
         uint64_t* base = (uint64_t*)ln.io.ptr;
         if (hipMemcpyAsync(base, seed, sw * 8, hipMemcpyHostToDevice, ln.stream) != hipSuccess ||
@@ -903,7 +928,7 @@ pa_status pa_hash_select(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t
     // scratch: reversed key | indices | result bits (256-byte aligned sections)
     auto up = [](uint64_t b) { return (b + 255) & ~uint64_t(255); };
     const uint64_t kr_bytes = up(direct_key_words(n) * 4), idx_bytes = up(count * 8), res_words = words_of(count);
-    pa_status s = ln.aux.ensure(c, kr_bytes + idx_bytes + res_words * 8);
+    pa_status s = ln.aux.ensure(c, kr_bytes + idx_bytes + res_words * 8, ln.stream);
     if (s == PA_OK) s = ln.jobs_host.ensure(idx_bytes + res_words * 8);
     if (s != PA_OK) return s;
     uint8_t* dbase = (uint8_t*)ln.aux.ptr;

@@ -20,11 +20,16 @@ namespace pa {
 
 struct Ctx;
 
-// Device allocation charged to the context's HBM budget.
+// Device allocation charged to the context's HBM budget.  A buffer that one
+// stream's work uses (a lane's workspace) is allocated and freed in that
+// stream's order (hipMallocAsync / hipFreeAsync), so growing it waits for
+// nothing else on the device; other buffers are freed after a device-wide
+// synchronisation.
 struct DevBuf {
     void* ptr = nullptr;
     size_t bytes = 0;
-    pa_status ensure(Ctx* c, size_t need);
+    hipStream_t owner = nullptr;
+    pa_status ensure(Ctx* c, size_t need, hipStream_t stream = nullptr);
     void release(Ctx* c);
 };
 
@@ -90,6 +95,7 @@ struct Request {
     uint64_t ticket = 0;
     uint32_t seed_id = 0;
     uint64_t n = 0, m = 0;
+    const uint64_t* seed = nullptr;   // device copy of the registered seed
     const uint64_t* key = nullptr;
     uint64_t* out = nullptr;
     double t_submit = 0, t_done = 0;
@@ -112,6 +118,7 @@ struct Ctx {
     std::mutex plan_mu;
     std::map<std::tuple<uint64_t, uint64_t, int, int, int>, TilePlan> plans;
     bool plan_cached(uint64_t n, uint64_t m, int policy, TilePlan* out);
+    bool pools = false;   // stream-ordered allocation supported on the device
     pa_stats last{};
 
     pa_status tables(int prec, int logL, Tables* out);
@@ -121,7 +128,7 @@ struct Ctx {
     std::condition_variable scv, done_cv;
     std::deque<Request*> pending;
     std::map<uint64_t, Request*> requests;
-    std::vector<DevBuf> seeds;
+    std::deque<DevBuf> seeds;      // a deque: registering a seed moves no other
     std::vector<uint64_t> seed_bits;
     std::vector<Lane> lanes;
     std::vector<std::vector<Request*>> lane_reqs;
@@ -140,6 +147,8 @@ const char* status_name(pa_status s);
 int policy_of(uint32_t flags);
 uint32_t prec_flag(int prec);
 void fill_plan_stats(pa_stats* s, const TilePlan& p);
+// Settle pa_stats.certified once a call has ended with status st.
+void set_certified(pa_stats* s, pa_status st);
 void fill_job(JobDesc* jd, const uint64_t* seed, const uint64_t* key, uint64_t* out, uint64_t n, uint64_t m,
               const TilePlan& p);
 double now_seconds();

@@ -124,12 +124,23 @@ double error_bound(int prec, int logL, uint64_t Bi) {
            5.0 * box_leak_rms(prec, logL, Bi);
 }
 
+// Worst-case bound of Percival's form (Math. Comp. 72, 2003): an FFT
+// convolution of a and b whose 3k radix-2 levels each add a relative error of
+// at most (1+u) for the additions, (1+u sqrt5) for a complex product and
+// (1+beta) for the twiddle (beta = 2u: table roots rounded once, four-step
+// roots an FP64 product rounded once) has max error at most
+// ||a|| ||b|| ((1+u)^3k (1+u sqrt5)^(3k+1) (1+beta)^3k - 1).  Read for this
+// pipeline: radix-4/8/16 stages count as their radix-2 levels, the spectrum
+// separation and the half-length Hermitian inverse add two levels (3k+2),
+// and the two sequences share one transform, so ||a|| ||b|| is replaced by
+// (||x|| + ||w||)^2 with ||x|| <= sqrt(Bi) (0/1 chunk) and ||w|| =
+// sqrt(Bi+Bo-1) (+-1 seed slice).  It holds for every input bit pattern.
 double rigorous_bound(int prec, int logL, uint64_t Bi, uint64_t Bo) {
-    if (prec == PREC_NTT) return 0.0;
-    const double u = unit_roundoff(prec), k = (double)logL, beta = 2.0 * u;
-    const double g = 3 * k * std::log1p(u) + (3 * k + 1) * std::log1p(u * std::sqrt(5.0)) +
-                     3 * k * std::log1p(beta);
-    return std::sqrt((double)Bi) * std::sqrt((double)(Bi + Bo - 1)) * std::expm1(g);
+    if (prec == PREC_NTT || prec == PREC_DIRECT) return 0.0;
+    const double u = unit_roundoff(prec), lv = 3.0 * logL + 2.0, beta = 2.0 * u;
+    const double g = lv * std::log1p(u) + (lv + 1) * std::log1p(u * std::sqrt(5.0)) + lv * std::log1p(beta);
+    const double norms = std::sqrt((double)Bi) + std::sqrt((double)(Bi + Bo - 1));
+    return norms * norms * std::expm1(g);
 }
 
 CostModel::CostModel() {
@@ -205,6 +216,7 @@ bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& 
     }
     if (!found) return false;
     best.bound = error_bound(prec, logL, best.Bi);
+    best.rigorous = rigorous_bound(prec, logL, best.Bi, best.Bo);
     if (best.bound > kPlanErrorLimit) return false;   // not reached by FP32 up to 2^24
     best.cost = (double)best.tiles() * cm.tile(prec, logL) + cm.launch_s;
     *out = best;

@@ -33,6 +33,7 @@ struct TilePlan {
     int prec = 0, logL = 0;
     uint64_t Bi = 0, Bo = 0, nchunks = 0, nouts = 0;
     double bound = 0, cost = 0;
+    double rigorous = 0;   // worst-case rounding bound of a tile (any input bits)
     uint64_t tiles() const { return nchunks * nouts; }
 };
 
@@ -43,9 +44,12 @@ struct TilePlan {
 // chunk's zero padding causes (about 0.036 u L once Bi > L/3; the larger term
 // from 2^22 on in FP32).
 double error_bound(int prec, int logL, uint64_t Bi);
-// Worst-case (a-priori) bound: ||x|| ||w|| times the relative error growth of
-// the FFT, product and inverse FFT, with ||x|| <= sqrt(Bi), ||w|| = sqrt(Bi+Bo-1).
+// Worst-case (a-priori) bound of a tile's max error for any input bits:
+// (||x|| + ||w||)^2 times the relative error growth of the forward FFT,
+// product and inverse FFT, with ||x|| <= sqrt(Bi), ||w|| = sqrt(Bi+Bo-1).  A
+// tile whose bound is below 0.5 rounds to the exact integers.
 double rigorous_bound(int prec, int logL, uint64_t Bi, uint64_t Bo);
+constexpr double kRigorousLimit = 0.5;
 void set_error_kappa(double kappa);
 double error_kappa();
 

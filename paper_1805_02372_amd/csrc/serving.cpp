@@ -68,6 +68,18 @@ static uint64_t request_bytes(Ctx* c, uint64_t n, uint64_t m, uint64_t* min_byte
     return p.tiles() * *min_bytes;
 }
 
+// Whether AUTO puts request (n, m) on the direct GF(2) path (short outputs).
+static bool request_direct(Ctx* c, uint64_t n, uint64_t m) {
+    TilePlan p;
+    if (!c->plan_cached(n, m, PREC_FP32, &p)) return false;
+    CostModel cm;
+    {
+        std::lock_guard<std::mutex> pl(c->plan_mu);
+        cm = c->cost;
+    }
+    return choose_direct(PA_PREC_AUTO, n, m, cm, p);
+}
+
 void Ctx::serve_loop() {
     (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(smu);
@@ -93,11 +105,13 @@ void Ctx::serve_loop() {
             {
                 const pa_stats& x = lane_stats[i];
                 serve_total.tiles += x.tiles;
+                serve_total.direct_jobs += x.direct_jobs;
                 serve_total.fallback_tiles += x.fallback_tiles;
                 serve_total.launches += x.launches;
                 serve_total.model_bytes += x.model_bytes;
                 serve_total.max_residual = std::max(serve_total.max_residual, x.max_residual);
                 serve_total.max_abs = std::max(serve_total.max_abs, x.max_abs);
+                serve_total.rigorous_bound = std::max(serve_total.rigorous_bound, x.rigorous_bound);
             }
             for (size_t k = 0; k < reqs.size(); ++k) {
                 reqs[k]->status = (s == PA_OK || s == PA_EPRECISION) ? per[k] : s;
@@ -112,7 +126,9 @@ void Ctx::serve_loop() {
         for (size_t i = 0; i < lanes.size() && !pending.empty() && !stop; ++i) {
             if (busy[i]) continue;
             // continuous batching: the oldest request and the waiting requests
-            // of its length class (within a scan window), up to the lane's budget
+            // of its kind (within a scan window), up to the lane's budget.  A
+            // kind is a length class, or the direct path (cls = 0) for the
+            // short outputs that AUTO gives it
             std::vector<Request*> batch;
             uint64_t bytes = 0;
             int cls0 = 0;
@@ -128,7 +144,12 @@ void Ctx::serve_loop() {
                 ++scanned;
                 uint64_t bmin = 0;
                 int cls = 0;
-                const uint64_t b = request_bytes(this, r->n, r->m, &bmin, &cls);
+                uint64_t b;
+                if (request_direct(this, r->n, r->m)) {
+                    b = bmin = ((r->n + 127) / 128) * 16;   // the reversed key
+                } else {
+                    b = request_bytes(this, r->n, r->m, &bmin, &cls);
+                }
                 if (bmin > budget) {
                     r->status = PA_ENOMEM;
                     r->t_done = now_seconds();
@@ -153,6 +174,35 @@ void Ctx::serve_loop() {
                 ms.push_back(r->m);
             }
             lk.unlock();
+            if (cls0 == 0) {
+                // direct products, one after another on the lane's stream
+                Lane& ln = lanes[i];
+                lane_stats[i] = pa_stats{};
+                pa_status s = PA_OK;
+                for (size_t k = 0; k < batch.size() && s == PA_OK; ++k)
+                    s = ln.direct(this, batch[k]->seed, batch[k]->key, ns[k], ms[k], batch[k]->out, false,
+                                  &lane_stats[i]);
+                ln.jobs.clear();
+                ln.total_tiles = 0;
+                if (s == PA_OK && !ln.done && hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess)
+                    s = PA_EDEVICE;
+                if (s == PA_OK && hipEventRecord(ln.done, ln.stream) != hipSuccess) s = PA_EDEVICE;
+                lk.lock();
+                if (s != PA_OK) {
+                    const double t = now_seconds();
+                    for (Request* r : batch) {
+                        r->status = s;
+                        r->t_done = t;
+                        r->state = 2;
+                    }
+                    done_cv.notify_all();
+                } else {
+                    lane_reqs[i] = batch;
+                    busy[i] = 1;
+                    any_busy = true;
+                }
+                continue;
+            }
             const int logL = cls0;
             CostModel cm;
             {
@@ -166,7 +216,7 @@ void Ctx::serve_loop() {
             std::vector<JobDesc> jobs(batch.size());
             if (s == PA_OK) {
                 for (size_t k = 0; k < batch.size(); ++k)
-                    fill_job(&jobs[k], (const uint64_t*)seeds[batch[k]->seed_id].ptr, batch[k]->key, batch[k]->out,
+                    fill_job(&jobs[k], batch[k]->seed, batch[k]->key, batch[k]->out,
                              batch[k]->n, batch[k]->m, plans[k]);
                 lane_stats[i] = pa_stats{};
                 for (const TilePlan& tp : plans) fill_plan_stats(&lane_stats[i], tp);
@@ -263,6 +313,7 @@ pa_status pa_submit(pa_ctx* ctx, uint32_t seed_id, uint64_t n, uint64_t m, const
     Request* r = new Request();
     r->ticket = c->next_ticket++;
     r->seed_id = seed_id;
+    r->seed = (const uint64_t*)c->seeds[seed_id].ptr;   // read under smu: registration may run concurrently
     r->n = n;
     r->m = m;
     r->key = key;
@@ -302,6 +353,19 @@ pa_status pa_serve_stats(pa_ctx* ctx, pa_stats* stats) {
     Ctx* c = reinterpret_cast<Ctx*>(ctx);
     std::lock_guard<std::mutex> lk(c->smu);
     *stats = c->serve_total;
+    stats->live_requests = c->requests.size();
+    return PA_OK;
+}
+
+pa_status pa_ticket_release(pa_ctx* ctx, uint64_t ticket) {
+    if (!ctx) return PA_EINVAL;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    std::lock_guard<std::mutex> lk(c->smu);
+    auto it = c->requests.find(ticket);
+    if (it == c->requests.end()) return PA_EINVAL;
+    if (it->second->state != 2) return PA_ENOTREADY;
+    delete it->second;
+    c->requests.erase(it);
     return PA_OK;
 }
 

@@ -37,8 +37,8 @@ pa_status pa_stream_open(pa_ctx* ctx, uint64_t n, uint64_t m, uint32_t flags, pa
     s->flags = flags;
     std::lock_guard<std::mutex> lk(c->mu);
     pa_status st = hipSetDevice(c->device) == hipSuccess ? PA_OK : PA_EDEVICE;
-    if (st == PA_OK) st = s->acc.ensure(c, nwords(m) * 8);
-    if (st == PA_OK) st = s->part.ensure(c, nwords(m) * 8);
+    if (st == PA_OK) st = s->acc.ensure(c, nwords(m) * 8, c->main.stream);
+    if (st == PA_OK) st = s->part.ensure(c, nwords(m) * 8, c->main.stream);
     // x ^ x = 0: clear the accumulator with the XOR kernel itself
     if (st == PA_OK && launch_xor_words((uint64_t*)s->acc.ptr, (const uint64_t*)s->acc.ptr, nwords(m), c->main.stream))
         st = PA_EDEVICE;
@@ -63,7 +63,7 @@ pa_status pa_stream_feed(pa_stream* s, const uint64_t* key_block, uint64_t lo, u
         std::lock_guard<std::mutex> lk(c->mu);
         if (hipSetDevice(c->device) != hipSuccess) return PA_EDEVICE;
         if (!(s->flags & PA_DEVICE_PTRS)) {   // stage the block in device memory
-            pa_status st = s->in.ensure(c, (sw + kw) * 8);
+            pa_status st = s->in.ensure(c, (sw + kw) * 8, c->main.stream);
             if (st != PA_OK) return st;
             uint64_t* base = (uint64_t*)s->in.ptr;
             if (hipMemcpyAsync(base, seed_block, sw * 8, hipMemcpyHostToDevice, c->main.stream) != hipSuccess ||

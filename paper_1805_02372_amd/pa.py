@@ -41,6 +41,7 @@ PA_PREC_MASK = 0x00F0
 PA_NO_FALLBACK = 0x0100
 PA_ASYNC = 0x0200
 PA_TIMING = 0x0400
+PA_CERT_NONE, PA_CERT_EXACT, PA_CERT_A_PRIORI, PA_CERT_A_POSTERIORI = range(4)
 
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 
@@ -56,7 +57,8 @@ class pa_stats(ctypes.Structure):
                 ("tiles", ctypes.c_uint64), ("fallback_tiles", ctypes.c_uint64),
                 ("max_residual", ctypes.c_double), ("max_abs", ctypes.c_double), ("bound", ctypes.c_double),
                 ("ms_pass", ctypes.c_double * 4), ("model_bytes", ctypes.c_uint64), ("launches", ctypes.c_uint64),
-                ("direct_jobs", ctypes.c_uint64)]
+                ("direct_jobs", ctypes.c_uint64), ("rigorous_bound", ctypes.c_double), ("certified", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("live_requests", ctypes.c_uint64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -69,7 +71,7 @@ class pa_plan(ctypes.Structure):
                 ("n2", ctypes.c_uint32), ("chunk_bits", ctypes.c_uint64), ("window_bits", ctypes.c_uint64),
                 ("chunks", ctypes.c_uint64), ("windows", ctypes.c_uint64), ("bound", ctypes.c_double),
                 ("cost", ctypes.c_double), ("direct_cost", ctypes.c_double), ("direct", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("reserved", ctypes.c_uint32), ("rigorous_bound", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -96,6 +98,7 @@ _sig = {
     "pa_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]),
     "pa_wait": (ctypes.c_int, [_P, ctypes.c_uint64]),
     "pa_ticket_latency": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]),
+    "pa_ticket_release": (ctypes.c_int, [_P, ctypes.c_uint64]),
     "pa_last_stats": (ctypes.c_int, [_P, ctypes.POINTER(pa_stats)]),
     "pa_serve_stats": (ctypes.c_int, [_P, ctypes.POINTER(pa_stats)]),
     "pa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -255,6 +258,11 @@ def pa_ticket_latency(ctx, ticket: int) -> float:
     s = ctypes.c_double()
     _check(_lib.pa_ticket_latency(ctx, int(ticket), ctypes.byref(s)), "pa_ticket_latency")
     return float(s.value)
+
+
+def pa_ticket_release(ctx, ticket: int) -> int:
+    """Free a finished ticket's record.  Returns the status."""
+    return _lib.pa_ticket_release(ctx, int(ticket))
 
 
 def pa_last_stats(ctx) -> dict:

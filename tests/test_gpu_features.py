@@ -268,6 +268,48 @@ def test_serving_tight_budget_admission(pa):
         pa.pa_destroy(c)
 
 
+def test_serving_release_many_small_requests(pa):
+    """2,000 small requests (short outputs go to the direct product, the rest
+    to FP32 tiles), each exact against the oracle; releasing every finished
+    ticket brings the held request records back to zero."""
+    import torch
+    from gpu_util import to_dev, empty_dev, from_dev
+    c = pa.pa_create(0, 0, None)
+    try:
+        rng = np.random.default_rng(44)
+        seed_bits = 300_000
+        seed = synth.gen_bits(rng, seed_bits)
+        sid = pa.pa_seed_register(c, to_dev(seed), seed_bits)
+        done = 0
+        for block in range(4):      # 4 x 500 requests in flight at once
+            reqs, tickets = [], []
+            for _ in range(500):
+                n = int(10 ** rng.uniform(3, 5))
+                m = max(1, int(n * rng.uniform(0.02, 0.5)))
+                key = synth.gen_bits(rng, n)
+                kd, od = to_dev(key), empty_dev(synth.words_for(m))
+                st, t = pa.pa_submit(c, sid, n, m, kd, od)
+                assert st == pa.PA_OK, pa.pa_strerror(st)
+                reqs.append((n, m, key, kd, od))
+                tickets.append(t)
+            assert all(pa.pa_wait(c, t) == pa.PA_OK for t in tickets)
+            torch.cuda.synchronize()
+            assert pa.pa_serve_stats(c)["live_requests"] == 500
+            for (n, m, key, kd, od), t in zip(reqs, tickets):
+                y = from_dev(od)[: synth.words_for(m)]
+                assert np.array_equal(y, oracle.hash_words(seed, n, m, key)), (n, m)
+                assert pa.pa_ticket_latency(c, t) > 0
+                assert pa.pa_ticket_release(c, t) == pa.PA_OK
+                done += 1
+            assert pa.pa_serve_stats(c)["live_requests"] == 0
+        st = pa.pa_serve_stats(c)
+        assert done == 2000 and st["direct_jobs"] > 0 and st["tiles"] > 0, st
+        assert pa.pa_ticket_release(c, tickets[0]) == pa.PA_EINVAL     # already released
+        assert pa.pa_wait(c, tickets[0]) == pa.PA_EINVAL
+    finally:
+        pa.pa_destroy(c)
+
+
 def test_serving_rejects_oversized_request(pa, ctx):
     from gpu_util import to_dev, empty_dev
     rng = np.random.default_rng(43)

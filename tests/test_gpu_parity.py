@@ -191,6 +191,13 @@ def test_random_shapes_every_path(pa, ctx, n, m):
         st, y = _run(pa, ctx, p, flags)
         assert st == pa.PA_OK, (prec, pa.pa_strerror(st))
         assert np.array_equal(y, ref), f"{prec}: " + describe(y, ref, m)
+        s = pa.pa_last_stats(ctx)
+        if prec in ("ntt", "direct") or s["prec"] in (pa.PA_PREC_NTT, pa.PA_PREC_DIRECT):
+            assert s["certified"] == pa.PA_CERT_EXACT, (prec, s)
+        else:
+            a_priori = s["rigorous_bound"] < 0.5
+            assert s["certified"] == (pa.PA_CERT_A_PRIORI if a_priori else pa.PA_CERT_A_POSTERIORI), (prec, s)
+            assert s["max_residual"] <= s["rigorous_bound"], (prec, s)
 
 
 GUARD = 8

@@ -1,0 +1,247 @@
+"""Oracle parity at full scale (MI355X, through the C ABI).
+
+* Long length classes (2^22, 2^23, 2^24) pinned by the class limits, with
+  outputs longer than half the FFT length so that plans have several key
+  chunks (XOR-accumulated, Eq. 4-7) and several output windows.
+* The shapes of the paper's Table 1 (section 4: 4 to 128 Mbit keys, outputs a
+  tenth of the key).
+* Requests of the serving stream at its own scale (keys up to 10^8 bits on
+  resident seeds of 1.5 * 10^8 bits), plus a request that fails the FP32
+  certificate inside a serving batch and is re-run in FP64.
+
+Where the whole output is too long for the oracle, outputs are checked one by
+one with the oracle's selected-output evaluation of the definition: both ends
+of the output, both sides of every output-window boundary, and random
+positions.  Nothing here compares the GPU with itself.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FULL_ORACLE_NM = 1e13    # n*m up to this: the whole output by the oracle (seconds on 16 threads)
+
+
+@pytest.fixture(scope="module")
+def pa():
+    from paper_1805_02372_amd import pa as _pa
+    return _pa
+
+
+@pytest.fixture(scope="module")
+def ctx(pa):
+    import torch
+    assert torch.cuda.is_available()
+    c = pa.pa_create(0, 0, None)
+    yield c
+    pa.pa_destroy(c)
+
+
+def sample_indices(m: int, bo: int, rng, random_count: int = 2000, edge: int = 256, boundary: int = 64):
+    """Output positions to check: both ends, both sides of every window
+    boundary o * bo, and random positions."""
+    parts = [np.arange(min(m, edge)), np.arange(max(0, m - edge), m)]
+    if 0 < bo < m:
+        for b in range(bo, m, bo):
+            parts.append(np.arange(max(0, b - boundary), min(m, b + boundary)))
+    parts.append(rng.integers(0, m, random_count))
+    return np.unique(np.concatenate(parts)).astype(np.uint64)
+
+
+def oracle_select(seed, n, m, key, idx, threads: int = 16):
+    """oracle.hash_select split over host threads (the C call releases the GIL)."""
+    chunks = [c for c in np.array_split(idx, threads) if c.size]
+    with cf.ThreadPoolExecutor(len(chunks)) as ex:
+        parts = list(ex.map(lambda c: oracle.hash_select(seed, n, m, key, c), chunks))
+    return np.concatenate(parts)
+
+
+def check_against_oracle(seed, n, m, key, y, window_bits, rng, what: str):
+    """Whole output when the oracle finishes in seconds, else sampled outputs;
+    bits past m in the last word must be zero either way."""
+    if m % 64:
+        assert int(y[-1]) >> (m % 64) == 0, f"{what}: bits past m are set"
+    if n * m <= FULL_ORACLE_NM:
+        from gpu_util import describe
+        ref = oracle.hash_words(seed, n, m, key)
+        assert np.array_equal(y, ref), f"{what}: " + describe(y, ref, m)
+        return m
+    idx = sample_indices(m, window_bits, rng)
+    ref = oracle_select(seed, n, m, key, idx)
+    got = synth.bits_to_array(y, m)[idx.astype(np.int64)]
+    bad = np.flatnonzero(got != ref)
+    assert bad.size == 0, f"{what}: {bad.size} of {idx.size} sampled bits differ, first at {idx[bad[:8]].tolist()}"
+    return int(idx.size)
+
+
+def _hash(pa, ctx, p, flags):
+    from gpu_util import to_dev, empty_dev, from_dev
+    import torch
+    print(f"case n={p.n} m={p.m} flags={flags:#x}", flush=True)
+    out = empty_dev(synth.words_for(p.m))
+    st = pa.pa_hash(ctx, to_dev(p.seed), p.n, p.m, to_dev(p.key), out, flags)
+    torch.cuda.synchronize()
+    return st, from_dev(out)[: synth.words_for(p.m)]
+
+
+# ---------------------------------------------------------------- long classes
+
+# (class, n, m): m > L/2, so the cheapest plan at the class has several output
+# windows and several key chunks
+FORCED = [(22, 6_000_000, 3_500_000), (23, 12_000_000, 7_000_000), (24, 40_000_000, 12_000_000),
+          (21, 1_500_000, 1_800_000)]
+
+
+@pytest.mark.parametrize("cls,n,m", FORCED)
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_forced_chunks_and_windows_long_classes(pa, ctx, cls, n, m, prec, monkeypatch):
+    monkeypatch.setenv("PA_MIN_LOG2_LEN", str(cls))
+    monkeypatch.setenv("PA_MAX_LOG2_LEN", str(cls))
+    flags = pa.PA_PREC_FP32_SEG if prec == "fp32" else pa.PA_PREC_FP64
+    plan = pa.pa_plan_query(n, m, flags)
+    assert plan["log2_len"] == cls and plan["chunks"] > 1 and plan["windows"] > 1, plan
+    rng = np.random.default_rng(cls * 7919 + n % 1009 + m % 1013)
+    p = synth.random_problem(rng, n, m)
+    st, y = _hash(pa, ctx, p, flags)
+    assert st == pa.PA_OK, pa.pa_strerror(st)
+    s = pa.pa_last_stats(ctx)
+    assert s["tiles"] >= plan["chunks"] * plan["windows"], (s, plan)
+    if s["fallback_tiles"] == 0:
+        assert s["tiles"] == plan["chunks"] * plan["windows"], (s, plan)
+    if prec == "fp64":
+        # the worst-case bound holds and certifies the plan a priori
+        assert s["max_residual"] <= s["rigorous_bound"] < 0.5 and s["certified"] == pa.PA_CERT_A_PRIORI, s
+    else:
+        assert s["certified"] == pa.PA_CERT_A_POSTERIORI, s
+    checked = check_against_oracle(p.seed, n, m, p.key, y, plan["window_bits"], rng, f"{prec} class {cls}")
+    print(prec, cls, n, m, "plan", plan["chunks"], "x", plan["windows"], "checked", checked,
+          "residual", s["max_residual"], "fallback", s["fallback_tiles"], flush=True)
+
+
+# ---------------------------------------------------------------- Table 1
+
+TABLE1_MBIT = [4, 8, 16, 32, 64, 128]
+
+
+@pytest.mark.parametrize("mbit", TABLE1_MBIT)
+def test_table1_shapes(pa, ctx, mbit):
+    """Section 4, Table 1: n = 4..128 * 10^6 key bits, m = n / 10, the plan
+    AUTO picks (the bench's sweep)."""
+    n = mbit * 1_000_000
+    m = n // 10
+    rng = np.random.default_rng(1000 + mbit)
+    p = synth.random_problem(rng, n, m)
+    st, y = _hash(pa, ctx, p, pa.PA_PREC_AUTO)
+    assert st == pa.PA_OK, pa.pa_strerror(st)
+    s = pa.pa_last_stats(ctx)
+    checked = check_against_oracle(p.seed, n, m, p.key, y, s["window_bits"], rng, f"table 1, {mbit} Mbit")
+    print("table1", mbit, "Mbit: class", s["log2_len"], "tiles", s["tiles"], "checked", checked, flush=True)
+
+
+# ---------------------------------------------------------------- serving at scale
+
+def _pick_requests(reqs, count):
+    """The largest request, the one with the most output bits, and the rest
+    spread evenly over the requests sorted by key length."""
+    order = sorted(range(len(reqs)), key=lambda i: reqs[i]["n"])
+    pick = {order[-1], max(range(len(reqs)), key=lambda i: reqs[i]["m"])}
+    for q in np.linspace(0, len(order) - 1, count):
+        if len(pick) >= count:
+            break
+        pick.add(order[int(q)])
+    return sorted(pick)
+
+
+def test_serving_stream_at_scale(pa):
+    """Requests of the serving workload (n log-uniform in [1e5, 1e8], m/n in
+    [0.02, 0.5], 8 resident seeds of 1.5e8 bits) submitted together, with
+    their own keys; each checked against the oracle."""
+    import torch
+    from gpu_util import to_dev, empty_dev, from_dev
+    seeds, reqs = synth.serving_stream(2000)
+    picked = _pick_requests(reqs, 24)
+    assert max(reqs[i]["n"] for i in picked) == max(r["n"] for r in reqs)
+    c = pa.pa_create(0, 0, None)
+    try:
+        ids = [pa.pa_seed_register(c, to_dev(s), s.size * 64) for s in seeds]
+        bufs, tickets = [], []
+        for i in picked:
+            r = reqs[i]
+            key = synth.request_key(r)
+            kd, od = to_dev(key), empty_dev(synth.words_for(r["m"]))
+            print(f"submit request {i}: n={r['n']} m={r['m']} seed {r['seed_id']}", flush=True)
+            st, t = pa.pa_submit(c, ids[r["seed_id"]], r["n"], r["m"], kd, od)
+            assert st == pa.PA_OK, pa.pa_strerror(st)
+            bufs.append((key, kd, od))
+            tickets.append(t)
+        statuses = [pa.pa_wait(c, t) for t in tickets]
+        assert all(x == pa.PA_OK for x in statuses), statuses
+        torch.cuda.synchronize()
+        stats = pa.pa_serve_stats(c)
+        print("serve stats", stats, flush=True)
+        rng = np.random.default_rng(99)
+        for i, (key, kd, od) in zip(picked, bufs):
+            r = reqs[i]
+            y = from_dev(od)[: synth.words_for(r["m"])]
+            plan = pa.pa_plan_query(r["n"], r["m"], pa.PA_PREC_FP32_SEG)
+            checked = check_against_oracle(seeds[r["seed_id"]], r["n"], r["m"], key, y, plan["window_bits"], rng,
+                                           f"request {i} (n={r['n']}, m={r['m']})")
+            print(f"request {i}: n={r['n']} m={r['m']} class {plan['log2_len']} "
+                  f"{plan['chunks']}x{plan['windows']} tiles, {checked} outputs checked", flush=True)
+    finally:
+        pa.pa_destroy(c)
+
+
+def test_serving_fallback_in_batch(pa):
+    """A request on an all-ones seed gives |z| = weight of its key chunk, above
+    what the FP32 certificate accepts (2^20), so its tiles are re-run in FP64
+    inside the serving batch it shares with random requests.  All-ones seed:
+    every output is the parity of the key's weight (a closed form)."""
+    import torch
+    from gpu_util import to_dev, empty_dev, from_dev
+    rng = np.random.default_rng(2718)
+    seed_bits = 30_000_000
+    ones = synth.pattern_bits("ones", seed_bits)
+    rand = synth.gen_bits(rng, seed_bits)
+    c = pa.pa_create(0, 0, None)
+    try:
+        sid_ones = pa.pa_seed_register(c, to_dev(ones), seed_bits)
+        sid_rand = pa.pa_seed_register(c, to_dev(rand), seed_bits)
+        # the all-ones request first: it is the oldest when the batch is formed
+        shapes = [(sid_ones, 20_000_000, 1_000_000), (sid_ones, 3_000_000, 100_000),
+                  (sid_rand, 19_000_000, 900_000), (sid_rand, 2_000_000, 500_000), (sid_rand, 300_000, 40_000)]
+        bufs, tickets = [], []
+        for sid, n, m in shapes:
+            key = synth.gen_bits(rng, n)
+            kd, od = to_dev(key), empty_dev(synth.words_for(m))
+            st, t = pa.pa_submit(c, sid, n, m, kd, od)
+            assert st == pa.PA_OK
+            bufs.append((key, od))
+            tickets.append(t)
+        assert all(pa.pa_wait(c, t) == pa.PA_OK for t in tickets)
+        torch.cuda.synchronize()
+        stats = pa.pa_serve_stats(c)
+        assert stats["fallback_tiles"] > 0, stats
+        for (sid, n, m), (key, od) in zip(shapes, bufs):
+            y = from_dev(od)[: synth.words_for(m)]
+            if sid == sid_ones:
+                weight = int(np.unpackbits(key.view(np.uint8)).sum())
+                expect = np.full(m, weight & 1, np.uint8)
+                got = synth.bits_to_array(y, m)
+                assert np.array_equal(got, expect), f"all-ones seed n={n}: {int((got != expect).sum())} bits differ"
+                if m % 64:
+                    assert int(y[-1]) >> (m % 64) == 0
+            else:
+                plan = pa.pa_plan_query(n, m, pa.PA_PREC_FP32_SEG)
+                check_against_oracle(rand, n, m, key, y, plan["window_bits"], rng, f"random request n={n}")
+        print("fallback tiles", stats["fallback_tiles"], "of", stats["tiles"], flush=True)
+    finally:
+        pa.pa_destroy(c)

@@ -229,3 +229,40 @@ def test_class_caps(pa, monkeypatch):
     monkeypatch.setenv("PA_MIN_LOG2_LEN", "24")
     p = pa.pa_plan_query(1000, 1000, pa.PA_PREC_FP32_SEG)
     assert p["log2_len"] == 24
+
+
+def test_rigorous_bound_fp64_margin_and_monotone(pa):
+    """The worst-case rounding bound (Percival's form) certifies every FP64
+    plan with a wide margin, grows with the tile's length and its key and
+    output norms, and is zero for the exact NTT."""
+    prev = 0.0
+    for k in range(12, 25):
+        n = (1 << k) // 2
+        p = pa.pa_plan_query(n, n, pa.PA_PREC_FP64)
+        assert p["log2_len"] == k and p["chunks"] == 1
+        assert 0 < p["rigorous_bound"] < 1e-4, p      # 5000x below the rounding margin 0.5
+        assert p["rigorous_bound"] > prev
+        prev = p["rigorous_bound"]
+    for n, m in SHAPES:
+        assert pa.pa_plan_query(n, m, pa.PA_PREC_FP64)["rigorous_bound"] < 1e-4
+        assert pa.pa_plan_query(n, m, pa.PA_PREC_NTT)["rigorous_bound"] == 0.0
+    # at a fixed class, a longer key chunk or output window gives a larger bound
+    os.environ["PA_MIN_LOG2_LEN"] = os.environ["PA_MAX_LOG2_LEN"] = "16"
+    try:
+        a = pa.pa_plan_query(10_000, 1000, pa.PA_PREC_FP64)["rigorous_bound"]
+        b = pa.pa_plan_query(20_000, 1000, pa.PA_PREC_FP64)["rigorous_bound"]
+        c = pa.pa_plan_query(20_000, 30_000, pa.PA_PREC_FP64)["rigorous_bound"]
+    finally:
+        del os.environ["PA_MIN_LOG2_LEN"], os.environ["PA_MAX_LOG2_LEN"]
+    assert a < b < c
+
+
+def test_rigorous_bound_fp32(pa):
+    """FP32: short tiles are certified a priori, the long tiles the fast path
+    uses are not (they rely on the run-time certificate); on full tiles the
+    worst case lies far above the probabilistic model."""
+    small = pa.pa_plan_query(1000, 333, pa.PA_PREC_FP32_SEG)
+    assert small["rigorous_bound"] < 0.5, small
+    c3 = pa.pa_plan_query(12_345_679, 1_234_567, pa.PA_PREC_FP32_SEG)
+    assert c3["rigorous_bound"] > 0.5, c3
+    assert c3["rigorous_bound"] > 100 * c3["bound"], c3
