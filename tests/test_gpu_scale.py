@@ -224,13 +224,15 @@ def test_serving_fallback_in_batch(pa):
             kd, od = to_dev(key), empty_dev(synth.words_for(m))
             st, t = pa.pa_submit(c, sid, n, m, kd, od)
             assert st == pa.PA_OK
-            bufs.append((key, od))
+            # the device key must stay alive until the request completes: the
+            # caching allocator would hand its memory to the next key
+            bufs.append((key, kd, od))
             tickets.append(t)
         assert all(pa.pa_wait(c, t) == pa.PA_OK for t in tickets)
         torch.cuda.synchronize()
         stats = pa.pa_serve_stats(c)
         assert stats["fallback_tiles"] > 0, stats
-        for (sid, n, m), (key, od) in zip(shapes, bufs):
+        for (sid, n, m), (key, _kd, od) in zip(shapes, bufs):
             y = from_dev(od)[: synth.words_for(m)]
             if sid == sid_ones:
                 weight = int(np.unpackbits(key.view(np.uint8)).sum())
