@@ -48,7 +48,8 @@ typedef enum {
     PA_EDEVICE = 3,      /* a HIP runtime error (no device, launch failure, ...) */
     PA_EPRECISION = 4,   /* a floating-point certificate failed, fallback off    */
     PA_EBUSY = 5,        /* serving queue full                                   */
-    PA_ENOTREADY = 6     /* ticket not finished (pa_poll)                         */
+    PA_ENOTREADY = 6,    /* ticket not finished (pa_poll)                         */
+    PA_ESCRATCH = 7      /* pa_hash_noalloc: the job exceeds its fixed scratch    */
 } pa_status;
 
 /* ---- flags ---------------------------------------------------------------- */
@@ -87,6 +88,32 @@ void pa_destroy(pa_ctx* ctx);
  * fails and PA_NO_FALLBACK is set. */
 pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m,
                   const uint64_t* key, uint64_t* out, uint32_t flags);
+
+/* pa_hash for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * operation, kernels and results as pa_hash with PA_DEVICE_PTRS; the call
+ * itself makes no hipMalloc, hipFree or other device or pinned allocation.
+ * The workspace, per-tile sums, certificates and twiddle tables live in one
+ * fixed array in device memory, about 133 MiB, that every GPU the library runs
+ * on holds until the process ends (its address is taken once per device when
+ * a context is created there).
+ * - seed, key, out: device pointers; flags must include PA_DEVICE_PTRS
+ *   (PA_EINVAL otherwise).  Precision bits, PA_NO_FALLBACK and PA_ASYNC as
+ *   for pa_hash; PA_TIMING is ignored.
+ * - Limits: FFT tiles of at most 2^23 points (so a failed FP32 tile can be
+ *   re-run in FP64 within the workspace), at most 16384 tiles per job, and
+ *   keys of at most 2^30 bits on the direct path; a job beyond them returns
+ *   PA_ESCRATCH before any work is queued.
+ * - Every call on one GPU shares that GPU's array, which keeps the last
+ *   call's contents.  Calls are serialised per device on the host, but calls
+ *   whose device work overlaps (PA_ASYNC, or contexts on different streams)
+ *   race on the array: order them on one stream or wait for each.
+ * - The first call for a length class builds its twiddle tables on the host
+ *   and copies them into the array (at most 8 classes are held; the least
+ *   recently used is replaced).
+ * pa_last_stats describes the call as for pa_hash. */
+pa_status pa_hash_noalloc(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m,
+                          const uint64_t* key, uint64_t* out, uint32_t flags);
 
 /* One job of a batch. */
 typedef struct {

@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libpa.so")
 ARCH = os.environ.get("PA_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["conv_fp32.hip", "conv_fp64.hip", "ntt.hip", "direct.hip", "classes.cpp",
-           "engine.cpp", "stream.cpp", "serving.cpp", "tuner.cpp", "planner.cpp", "tables.cpp"]
+           "engine.cpp", "noalloc.cpp", "stream.cpp", "serving.cpp", "tuner.cpp", "planner.cpp", "tables.cpp"]
 
 # Packed FP32 instructions are disabled for all device code.  Code object v5
 # loads in every ROCm 6/7 runtime, including the one PyTorch bundles.  Atomics

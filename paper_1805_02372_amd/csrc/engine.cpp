@@ -32,6 +32,7 @@ const char* status_name(pa_status s) {
         case PA_EPRECISION: return "PA_EPRECISION: floating-point certificate failed";
         case PA_EBUSY: return "PA_EBUSY: queue full";
         case PA_ENOTREADY: return "PA_ENOTREADY: not finished";
+        case PA_ESCRATCH: return "PA_ESCRATCH: beyond the fixed scratch array of pa_hash_noalloc";
     }
     return "unknown pa_status";
 }
@@ -42,6 +43,7 @@ static uint64_t words_of(uint64_t bits) { return (bits + 63) >> 6; }
 
 pa_status DevBuf::ensure(Ctx* c, size_t need, hipStream_t stream) {
     if (need <= bytes) return PA_OK;
+    if (fixed) return PA_ESCRATCH;
     release(c);
     size_t want = std::max(need, (size_t)256);
     uint64_t cur = c->used.load();
@@ -62,6 +64,7 @@ pa_status DevBuf::ensure(Ctx* c, size_t need, hipStream_t stream) {
 }
 
 void DevBuf::release(Ctx* c) {
+    if (fixed) return;
     if (ptr) {
         if (owner) {
             (void)hipFreeAsync(ptr, owner);   // after the owner's queued work
@@ -78,6 +81,7 @@ void DevBuf::release(Ctx* c) {
 
 pa_status HostBuf::ensure(size_t need) {
     if (need <= bytes) return PA_OK;
+    if (fixed) return PA_ESCRATCH;
     if (ptr) (void)hipHostFree(ptr);
     ptr = nullptr;
     bytes = 0;
@@ -91,6 +95,7 @@ pa_status HostBuf::ensure(size_t need) {
 }
 
 void HostBuf::release() {
+    if (fixed) return;
     if (ptr) (void)hipHostFree(ptr);
     ptr = nullptr;
     bytes = 0;
@@ -120,65 +125,80 @@ bool Ctx::plan_cached(uint64_t n, uint64_t m, int policy, TilePlan* out) {
     return true;
 }
 
+pa_status table_image(int prec, int logL, std::vector<unsigned char>* host, size_t off[6], int* fshift) {
+    ClassGeom g;
+    if (!class_geometry(prec, logL, &g)) return PA_EINVAL;
+    auto pack = [&](auto& th) {
+        using E = typename std::remove_reference<decltype(th.tw)>::type::value_type;
+        const void* src[6] = {th.tw.data(), th.fa.data(), th.fb.data(), th.stw.data(), th.fa64.data(),
+                              th.fb64.data()};
+        const size_t bytes[6] = {th.tw.size() * sizeof(E), th.fa.size() * sizeof(E), th.fb.size() * sizeof(E),
+                                 th.stw.size() * sizeof(E), th.fa64.size() * sizeof(double),
+                                 th.fb64.size() * sizeof(double)};
+        size_t total = 0;
+        for (int k = 0; k < 6; ++k) {
+            off[k] = total;
+            total += (bytes[k] + 255) & ~(size_t)255;
+        }
+        host->assign(total, 0);
+        for (int k = 0; k < 6; ++k)
+            if (bytes[k]) memcpy(host->data() + off[k], src[k], bytes[k]);
+        *fshift = th.fshift;
+    };
+    if (prec == PREC_NTT) {
+        TableHost<uint32_t> th;
+        build_ntt_tables(logL, g.n1, g.n2, &th);
+        pack(th);
+    } else if (prec == PREC_FP32) {
+        TableHost<float> th;
+        build_tables<float>(logL, g.n1, g.n2, &th);
+        pack(th);
+    } else {
+        TableHost<double> th;
+        build_tables<double>(logL, g.n1, g.n2, &th);
+        pack(th);
+    }
+    return PA_OK;
+}
+
+Tables table_view(int prec, unsigned char* base, const size_t off[6], int fshift) {
+    Tables t;
+    t.fshift = fshift;
+    t.tw = base + off[0];
+    t.fa = base + off[1];
+    t.fb = base + off[2];
+    t.stw = base + off[3];
+    // an FP32 class carries its own FP64 two-level tables; an FP64 class uses fa, fb
+    const bool own64 = prec == PREC_FP32;
+    t.fa64 = (const double*)(own64 ? base + off[4] : base + off[1]);
+    t.fb64 = (const double*)(own64 ? base + off[5] : base + off[2]);
+    return t;
+}
+
 pa_status Ctx::tables(int prec, int logL, Tables* out) {
     std::lock_guard<std::mutex> lk(tab_mu);
     const int key = prec * 100 + logL;
     auto it = tabs.find(key);
     if (it == tabs.end()) {
-        ClassGeom g;
-        if (!class_geometry(prec, logL, &g)) return PA_EINVAL;
-        DevTables dt;
-        // sections: tw, fa, fb, stw (element type of the class), then fa64,
-        // fb64 (FP64); each starts on a 256-byte boundary
         std::vector<unsigned char> host;
-        size_t off[6] = {0, 0, 0, 0, 0, 0};
-        auto pack = [&](auto& th) {
-            using E = typename std::remove_reference<decltype(th.tw)>::type::value_type;
-            const void* src[6] = {th.tw.data(), th.fa.data(), th.fb.data(), th.stw.data(), th.fa64.data(),
-                                  th.fb64.data()};
-            const size_t bytes[6] = {th.tw.size() * sizeof(E), th.fa.size() * sizeof(E), th.fb.size() * sizeof(E),
-                                     th.stw.size() * sizeof(E), th.fa64.size() * sizeof(double),
-                                     th.fb64.size() * sizeof(double)};
-            size_t total = 0;
-            for (int k = 0; k < 6; ++k) {
-                off[k] = total;
-                total += (bytes[k] + 255) & ~(size_t)255;
-            }
-            host.assign(total, 0);
-            for (int k = 0; k < 6; ++k)
-                if (bytes[k]) memcpy(host.data() + off[k], src[k], bytes[k]);
-            dt.t.fshift = th.fshift;
-        };
-        bool own64 = false;
-        if (prec == PREC_NTT) {
-            TableHost<uint32_t> th;
-            build_ntt_tables(logL, g.n1, g.n2, &th);
-            pack(th);
-        } else if (prec == PREC_FP32) {
-            TableHost<float> th;
-            build_tables<float>(logL, g.n1, g.n2, &th);
-            pack(th);
-            own64 = true;
-        } else {
-            TableHost<double> th;
-            build_tables<double>(logL, g.n1, g.n2, &th);
-            pack(th);
-        }
-        pa_status st = dt.buf.ensure(this, host.size());
+        size_t off[6];
+        int fshift = 0;
+        pa_status st = table_image(prec, logL, &host, off, &fshift);
+        if (st != PA_OK) return st;
+        DevTables dt;
+        st = dt.buf.ensure(this, host.size());
         if (st != PA_OK) return st;
         if (hipMemcpy(dt.buf.ptr, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess)
             return PA_EDEVICE;
-        unsigned char* base = (unsigned char*)dt.buf.ptr;
-        dt.t.tw = base + off[0];
-        dt.t.fa = base + off[1];
-        dt.t.fb = base + off[2];
-        dt.t.stw = base + off[3];
-        dt.t.fa64 = (const double*)(own64 ? base + off[4] : base + off[1]);
-        dt.t.fb64 = (const double*)(own64 ? base + off[5] : base + off[2]);
+        dt.t = table_view(prec, (unsigned char*)dt.buf.ptr, off, fshift);
         it = tabs.emplace(key, dt).first;
     }
     *out = it->second.t;
     return PA_OK;
+}
+
+pa_status lane_tables(Ctx* c, const Lane& ln, int prec, int logL, Tables* out) {
+    return ln.static_tables ? noalloc_tables(c->device, prec, logL, out) : c->tables(prec, logL, out);
 }
 
 // ------------------------------------------------------------ pass timing
@@ -278,7 +298,7 @@ pa_status Lane::launch(Ctx* c, int prec_, int logL_, std::vector<JobDesc>& js, b
         total += jd.nchunks * jd.nouts;
     }
     Tables tb;
-    pa_status st = c->tables(prec, logL, &tb);
+    pa_status st = lane_tables(c, *this, prec, logL, &tb);
     if (st != PA_OK) return st;
     st = meta.ensure(c, (size_t)total * sizeof(TileMeta), stream);
     if (st != PA_OK) return st;
@@ -295,7 +315,10 @@ pa_status Lane::launch(Ctx* c, int prec_, int logL_, std::vector<JobDesc>& js, b
     const size_t tile_bytes = ((size_t)1 << cfg.logL) * elt;
     const size_t part_bytes = (size_t)(cfg.n1 / cfg.b1) * sizeof(uint32_t);
     size_t G = total;
-    if (ws.bytes < G * tile_bytes || part.bytes < G * part_bytes) {
+    if (ws.fixed) {   // a fixed workspace: as many tiles as it holds
+        G = std::min<size_t>(G, std::min<size_t>(ws.bytes / tile_bytes, part.bytes / part_bytes));
+        if (G == 0) return PA_ESCRATCH;
+    } else if (ws.bytes < G * tile_bytes || part.bytes < G * part_bytes) {
         const uint64_t u = c->used.load();
         const uint64_t mine = ws.bytes + part.bytes;
         uint64_t avail = c->budget > u ? c->budget - u + mine : mine;
@@ -400,8 +423,8 @@ pa_status Lane::finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_s
     //    cleared and rebuilt).
     const ClassKernels* K32 = class_kernels(PREC_FP32, logL);
     Tables tb, tb32;
-    pa_status st = c->tables(PREC_FP64, logL, &tb);
-    if (st == PA_OK) st = c->tables(PREC_FP32, logL, &tb32);
+    pa_status st = lane_tables(c, *this, PREC_FP64, logL, &tb);
+    if (st == PA_OK) st = lane_tables(c, *this, PREC_FP32, logL, &tb32);
     if (st != PA_OK) return st;
     st = ws.ensure(c, ((size_t)1 << logL) * 16, stream);
     if (st != PA_OK) return st;
@@ -565,6 +588,9 @@ pa_status pa_create(pa_ctx** out, int device, uint64_t budget, void* hip_stream)
         c->main.own_stream = true;
     }
     c->serving_init();
+    // the no-allocation entry's array: its device address, once per device
+    // (a failure here only disables pa_hash_noalloc, which then reports it)
+    (void)noalloc_setup(device);
     if (const char* tc = getenv("PA_TUNE_CACHE")) (void)tune_load(c, tc);  // optional
     *out = reinterpret_cast<pa_ctx*>(c);
     return PA_OK;

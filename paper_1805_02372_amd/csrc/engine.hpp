@@ -29,6 +29,8 @@ struct DevBuf {
     void* ptr = nullptr;
     size_t bytes = 0;
     hipStream_t owner = nullptr;
+    bool fixed = false;   // a view of memory owned elsewhere: never grown or freed
+                          // (ensure fails with PA_ESCRATCH beyond `bytes`)
     pa_status ensure(Ctx* c, size_t need, hipStream_t stream = nullptr);
     void release(Ctx* c);
 };
@@ -37,6 +39,7 @@ struct DevBuf {
 struct HostBuf {
     void* ptr = nullptr;
     size_t bytes = 0;
+    bool fixed = false;   // as DevBuf::fixed
     pa_status ensure(size_t need);
     void release();
 };
@@ -66,6 +69,7 @@ struct Lane {
     DevBuf aux;           // direct path: reversed key, selected indices and bits
     HostBuf meta_host, jobs_host;
     PassTimer timer;
+    bool static_tables = false;   // twiddle tables from the no-allocation entry's array
 
     // In-flight state of an asynchronous launch (serving).
     int prec = 0, logL = 0;
@@ -154,5 +158,19 @@ void fill_job(JobDesc* jd, const uint64_t* seed, const uint64_t* key, uint64_t* 
 double now_seconds();
 pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path);
 pa_status tune_load(Ctx* c, const char* path);
+
+// Twiddle tables of a length class as one host image: sections tw, fa, fb,
+// stw (element type of the class), fa64, fb64 (FP64), each on a 256-byte
+// boundary; `off` receives the section offsets.
+pa_status table_image(int prec, int logL, std::vector<unsigned char>* host, size_t off[6], int* fshift);
+// Device pointers of the sections of an image copied to `base`.
+Tables table_view(int prec, unsigned char* base, const size_t off[6], int fshift);
+// Tables of a class for a lane: the context's cache, or the no-allocation
+// entry's array (Lane::static_tables).
+pa_status lane_tables(Ctx* c, const Lane& ln, int prec, int logL, Tables* out);
+// No-allocation entry: per-device set-up (called by pa_create with the device
+// current) and its tables.
+pa_status noalloc_setup(int device);
+pa_status noalloc_tables(int device, int prec, int logL, Tables* out);
 
 }  // namespace pa

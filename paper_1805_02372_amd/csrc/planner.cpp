@@ -223,10 +223,10 @@ bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& 
     return true;
 }
 
-bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan* out) {
+bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan* out, int cap_logL) {
     if (n == 0 || m == 0) return false;
     const int prec = policy;
-    const int lo = min_logL(prec), hi = max_logL(prec);
+    const int lo = min_logL(prec), hi = std::min(max_logL(prec), cap_logL);
     if (prec == PREC_FP64 || prec == PREC_NTT) {
         // one tile at the smallest class that holds the whole product
         for (int k = lo; k <= hi; ++k)

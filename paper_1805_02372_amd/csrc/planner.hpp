@@ -69,9 +69,9 @@ bool choose_direct(uint32_t flags, uint64_t n, uint64_t m, const CostModel& cm, 
 bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& cm, TilePlan* out);
 
 // Best plan over classes for one job.  policy: PREC_FP32 (segmented, bound
-// limited), PREC_FP64 (smallest single tile if one fits, else the largest
-// class), PREC_NTT.
-bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan* out);
+// limited), PREC_FP64 (smallest single tile if one fits, else the cheapest
+// plan over the classes), PREC_NTT.  Classes above 2^cap_logL are not used.
+bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan* out, int cap_logL = 24);
 
 // Jobs of a batch that share one FFT length class (one pipeline launch).
 struct BatchGroup {

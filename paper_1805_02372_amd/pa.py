@@ -30,7 +30,7 @@ except ImportError:  # pragma: no cover - the library also works without torch
 _lib = ctypes.CDLL(LIB_PATH)
 
 # ---- constants (mirror include/pa.h)
-PA_OK, PA_EINVAL, PA_ENOMEM, PA_EDEVICE, PA_EPRECISION, PA_EBUSY, PA_ENOTREADY = range(7)
+PA_OK, PA_EINVAL, PA_ENOMEM, PA_EDEVICE, PA_EPRECISION, PA_EBUSY, PA_ENOTREADY, PA_ESCRATCH = range(8)
 PA_DEVICE_PTRS = 0x0001
 PA_PREC_AUTO = 0x0000
 PA_PREC_FP32_SEG = 0x0010
@@ -82,6 +82,7 @@ _sig = {
     "pa_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_uint64, _P]),
     "pa_destroy": (None, [_P]),
     "pa_hash": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, _P, _P, ctypes.c_uint32]),
+    "pa_hash_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, _P, _P, ctypes.c_uint32]),
     "pa_hash_batch": (ctypes.c_int, [_P, ctypes.POINTER(pa_job), ctypes.c_uint64, ctypes.c_uint32,
                                      ctypes.POINTER(ctypes.c_int)]),
     "pa_hash_select": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, _P, _P, ctypes.c_uint64, _P,
@@ -172,6 +173,12 @@ def pa_hash(ctx, seed, n: int, m: int, key, out, flags: int = 0) -> int:
     if _is_device(seed) and _is_device(key) and _is_device(out):
         flags |= PA_DEVICE_PTRS
     return _lib.pa_hash(ctx, _ptr(seed), int(n), int(m), _ptr(key), _ptr(out), int(flags))
+
+
+def pa_hash_noalloc(ctx, seed, n: int, m: int, key, out, flags: int = 0) -> int:
+    """pa_hash without device allocation (device tensors only; PA_DEVICE_PTRS
+    is added).  Returns the status."""
+    return _lib.pa_hash_noalloc(ctx, _ptr(seed), int(n), int(m), _ptr(key), _ptr(out), int(flags) | PA_DEVICE_PTRS)
 
 
 def pa_hash_batch(ctx, jobs, flags: int = 0):
