@@ -123,7 +123,9 @@ typedef struct {
     uint64_t n, m;
 } pa_job;
 
-/* Hash `count` independent jobs (uneven n and m).  Jobs are grouped by FFT
+/* Hash `count` independent jobs (uneven n and m): the paper runs the batches
+ * of a long key in parallel on the GPU and queues later work behind them
+ * (section 3, Fig. 2; section 4).  Here jobs are grouped by FFT
  * length class (each job's cheapest class, groups folded together while that
  * lowers the summed cost); each group runs as one launch per pipeline pass for
  * all its tiles.  The groups run concurrently on the context's stream and on

@@ -1,4 +1,5 @@
-// The Toeplitz-hash tile pipeline as three HIP kernels (plus an XOR merge).
+// The Toeplitz-hash tile pipeline as three HIP kernels with workgroup-wide
+// Stockham transforms (the short length classes).
 //
 // A tile convolves a seed slice w (bi+bo-1 bits, encoded +-1) with a key
 // chunk x (bi bits, encoded 0/1) circularly over L = n1*n2 >= bi+bo-1 points
