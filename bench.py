@@ -39,8 +39,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("conv_fp32.hip", "conv_fp64.hip", "conv_kernels.hpp", "conv_v2.hpp", "fft_core.hpp",
-                  "wave_fft.hpp", "ntt.hip", "pa_internal.hpp")
+KERNEL_SOURCES = ("conv_fp32.hip", "conv_fp64.hip", "conv_fp32_p3.hip", "conv_fp32_p5.hip", "conv_fp32_p7.hip",
+                  "conv_fp64_p3.hip", "conv_fp64_p5.hip", "conv_fp64_p7.hip", "conv_kernels.hpp", "conv_v2.hpp",
+                  "fft_core.hpp", "wave_fft.hpp", "ntt.hip", "pa_internal.hpp")
 
 
 def kernel_source_digest() -> str:
@@ -65,7 +66,7 @@ def launch_bytes(st: dict, n: int, m: int) -> list[float]:
               output window: 0.5 e L T + C m / 8
     The fourth entry (the former merge) is 0: chunks are XOR-accumulated."""
     e = 16 if st["prec"] == 0x20 else 8
-    L = float(1 << st["log2_len"])
+    L = float(st["fft_len"])
     C = -(-n // st["chunk_bits"])
     W = -(-m // st["window_bits"])
     T = C * W
@@ -121,7 +122,7 @@ def run_latency_c1(pa, ctx, torch, calls: int = 200, warmup: int = 20):
                   "mean_us": round(r["elapsed"] / calls * 1e6, 1),
                   "kernel_us": [round(x * 1e3, 2) for x in r["kernel_ms"][:3]],
                   "gbps": round(prob.n * calls / r["elapsed"] / 1e9, 3),
-                  "log2_len": st["log2_len"], "tiles": st["tiles"],
+                  "fft_len": st["fft_len"], "tiles": st["tiles"],
                   "rigorous_bound": st["rigorous_bound"], "certified": CERT_NAMES[st["certified"]],
                   "out": r["out"]}
 
@@ -141,7 +142,7 @@ def run_c2(pa, ctx, torch, steps, warmup):
                      "ms_per_call": round(r["elapsed"] / steps * 1e3, 4),
                      "p99_ms": round(float(np.percentile(r["lat"], 99)) * 1e3, 4),
                      "kernel_ms": [round(x, 5) for x in r["kernel_ms"][:3]],
-                     "log2_len": st["log2_len"], "chunk_bits": st["chunk_bits"], "window_bits": st["window_bits"],
+                     "fft_len": st["fft_len"], "chunk_bits": st["chunk_bits"], "window_bits": st["window_bits"],
                      "tiles": st["tiles"], "model_bound": st["bound"], "rigorous_bound": st["rigorous_bound"],
                      "max_residual": st["max_residual"], "fallback_tiles": st["fallback_tiles"],
                      "certified": CERT_NAMES[st["certified"]]}
@@ -344,7 +345,7 @@ def run_table1(pa, ctx, torch, reps: int = 5):
         assert st == pa.PA_OK, pa.pa_strerror(st)
         ok = bool(np.array_equal(ref, synth.bits_to_array(r["out"], m)[idx]))
         row = {"mbit": mb, "n": n, "m": m, "gbps": round(n * reps / r["elapsed"] / 1e9, 2),
-               "ms_per_call": round(r["elapsed"] / reps * 1e3, 3), "log2_len": r["stats"]["log2_len"],
+               "ms_per_call": round(r["elapsed"] / reps * 1e3, 3), "fft_len": r["stats"]["fft_len"],
                "tiles": r["stats"]["tiles"], "spot_check_exact": ok, "paper_titan_xp_gbps": paper}
         log(f"[bench] table-1 shape: {row}")
         out.append(row)
@@ -579,7 +580,7 @@ def main():
             "workload": "c3: one Toeplitz hash, n=12,345,679 key bits, m=1,234,567 output bits, "
                         "i.i.d. uniform bits (seed 2), inputs resident in HBM",
             "n": prob.n, "m": prob.m, "path": head_name,
-            "plan": {"log2_len": st["log2_len"], "n1": st["n1"], "n2": st["n2"], "tiles": tiles,
+            "plan": {"fft_len": st["fft_len"], "n1": st["n1"], "n2": st["n2"], "tiles": tiles,
                      "chunk_bits": st["chunk_bits"], "window_bits": st["window_bits"]},
         },
         "roofline": {
@@ -614,13 +615,13 @@ def main():
             "gbps": round(prob.n * args.steps / r["elapsed"] / 1e9, 3),
             "ms_per_step": round(r["elapsed"] / args.steps * 1e3, 4),
             "kernel_ms": [round(x, 5) for x in r["kernel_ms"]],
-            "log2_len": r["stats"]["log2_len"], "tiles": r["stats"]["tiles"],
+            "fft_len": r["stats"]["fft_len"], "tiles": r["stats"]["tiles"],
             "bit_exact": bool(r["bit_exact"]),
             "p99_ms": round(float(np.percentile(r["lat"], 99)) * 1e3, 4),
         }
     if batch is not None:
         line["batch_c4"] = {"jobs": 64, "gbps": round(batch["gbps"], 3), "tiles": batch["stats"]["tiles"],
-                            "log2_len": batch["stats"]["log2_len"], "bit_exact": bool(batch["bit_exact"]),
+                            "largest_fft_len": batch["stats"]["fft_len"], "bit_exact": bool(batch["bit_exact"]),
                             "fallback_tiles": batch["stats"]["fallback_tiles"],
                             "launches_per_batch": batch["stats"]["launches"],
                             "tuned": True, "tune_s": round(batch["tune_s"], 3),

@@ -245,7 +245,7 @@ pa_status pa_ticket_release(pa_ctx* ctx, uint64_t ticket);
 
 typedef struct {
     uint32_t prec;            /* PA_PREC_* of the plan that ran               */
-    uint32_t log2_len;        /* FFT length L = 2^log2_len                    */
+    uint32_t log2_len;        /* ceil(log2 L) of the FFT length L             */
     uint32_t n1, n2;          /* L = n1 * n2 (row and column lengths)         */
     uint64_t chunk_bits;      /* key bits per tile (Bi)                       */
     uint64_t window_bits;     /* output bits per tile (Bo)                    */
@@ -265,7 +265,8 @@ typedef struct {
     double rigorous_bound;    /* worst-case error bound of the FP plan (for any
                                  input bits); 0 for exact paths              */
     uint32_t certified;       /* how the result is known exact: PA_CERT_*     */
-    uint32_t reserved;
+    uint32_t fft_len;         /* the FFT length L: 2^k, or 3, 5 or 7 times 2^k
+                                 (mixed-radix classes, FP32 and FP64)        */
     uint64_t live_requests;   /* pa_serve_stats: request records held (queued,
                                  running, or finished and not yet released)  */
 } pa_stats;
@@ -307,7 +308,7 @@ pa_status pa_tune_load(pa_ctx* ctx, const char* path);
 
 typedef struct {
     uint32_t prec;        /* PA_PREC_FP32_SEG or PA_PREC_FP64 (or NTT)  */
-    uint32_t log2_len;    /* L = 2^log2_len                              */
+    uint32_t log2_len;    /* ceil(log2 L)                                */
     uint32_t n1, n2;
     uint64_t chunk_bits;  /* Bi: key bits per chunk (last chunk may be shorter) */
     uint64_t window_bits; /* Bo: output bits per window, multiple of 64 unless it is m */
@@ -318,7 +319,7 @@ typedef struct {
     double direct_cost;   /* model cost of the direct path for (n, m)    */
     uint32_t direct;      /* 1: the flags run (n, m) on the direct path; the
                              fields above still describe the FFT plan   */
-    uint32_t reserved;
+    uint32_t fft_len;     /* FFT length L of a tile                      */
     double rigorous_bound; /* worst-case rounding bound of one tile of the plan,
                               for any input bits (0 for NTT); below 0.5 the plan
                               is certified a priori                      */

@@ -16,7 +16,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpa.so")
 ARCH = os.environ.get("PA_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["conv_fp32.hip", "conv_fp64.hip", "ntt.hip", "direct.hip", "classes.cpp",
+SOURCES = ["conv_fp32.hip", "conv_fp64.hip", "conv_fp32_p3.hip", "conv_fp32_p5.hip", "conv_fp32_p7.hip",
+           "conv_fp64_p3.hip", "conv_fp64_p5.hip", "conv_fp64_p7.hip", "ntt.hip", "direct.hip", "classes.cpp",
            "engine.cpp", "noalloc.cpp", "stream.cpp", "serving.cpp", "tuner.cpp", "planner.cpp", "tables.cpp"]
 
 # Packed FP32 instructions are disabled for all device code.  Code object v5

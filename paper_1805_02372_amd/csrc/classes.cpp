@@ -1,5 +1,5 @@
 // Length-class dispatch (the per-precision tables live in conv_fp32.hip,
-// conv_fp64.hip and ntt.hip) and the device queries the launchers share.
+// conv_fp64.hip, conv_fp{32,64}_p{3,5,7}.hip and ntt.hip) and the device queries the launchers share.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -21,14 +21,31 @@ int row_pass_workgroups() {
     return cu;
 }
 
-const ClassKernels* class_kernels32(int logL);
-const ClassKernels* class_kernels64(int logL);
-const ClassKernels* class_kernels_ntt(int logL);
+const ClassKernels* class_kernels32(int cls);
+const ClassKernels* class_kernels64(int cls);
+const ClassKernels* class_kernels_ntt(int cls);
+const ClassKernels* class_kernels_fp32_p3(int cls);
+const ClassKernels* class_kernels_fp32_p5(int cls);
+const ClassKernels* class_kernels_fp32_p7(int cls);
+const ClassKernels* class_kernels_fp64_p3(int cls);
+const ClassKernels* class_kernels_fp64_p5(int cls);
+const ClassKernels* class_kernels_fp64_p7(int cls);
 
-const ClassKernels* class_kernels(int prec, int logL) {
-    if (prec == 32) return class_kernels32(logL);
-    if (prec == 64) return class_kernels64(logL);
-    if (prec == 1) return class_kernels_ntt(logL);
+static const ClassKernels* smooth_kernels(int prec, int cls) {
+    if (!smooth_valid(cls)) return nullptr;
+    const int P = smooth_P(cls);
+    if (prec == 32) return P == 3 ? class_kernels_fp32_p3(cls) : P == 5 ? class_kernels_fp32_p5(cls) : class_kernels_fp32_p7(cls);
+    if (prec == 64) return P == 3 ? class_kernels_fp64_p3(cls) : P == 5 ? class_kernels_fp64_p5(cls) : class_kernels_fp64_p7(cls);
+    return nullptr;
+}
+
+// Kernels of class `cls` (ids in pa_internal.hpp); the mixed-radix classes
+// exist for FP32 and FP64 only.
+const ClassKernels* class_kernels(int prec, int cls) {
+    const bool smooth = cls >= 32;
+    if (prec == 32) return smooth ? smooth_kernels(32, cls) : class_kernels32(cls);
+    if (prec == 64) return smooth ? smooth_kernels(64, cls) : class_kernels64(cls);
+    if (prec == 1) return smooth ? nullptr : class_kernels_ntt(cls);
     return nullptr;
 }
 

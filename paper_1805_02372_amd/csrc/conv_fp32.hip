@@ -8,8 +8,8 @@
 namespace pa {
 
 #define PA_CLASS(LOGL, N1, N2) \
-    {ClassCfg{32, LOGL, N1, N2, 8, 16, 16}, &ClassImpl<float, N1, N2, 8, 16, 16>::pass1, \
-     &ClassImpl<float, N1, N2, 8, 16, 16>::pass2, &ClassImpl<float, N1, N2, 8, 16, 16>::pass3}
+    {ClassCfg{32, LOGL, N1, N2, 8, 16, 16}, &ClassImpl<float, N1, N2, 8, 16, 16, 16>::pass1, \
+     &ClassImpl<float, N1, N2, 8, 16, 16, 16>::pass2, &ClassImpl<float, N1, N2, 8, 16, 16, 16>::pass3}
 #define PA_CLASS2(LOGL, N2) \
     {ClassCfg{32, LOGL, kN1, N2, ClassImpl2<float, N2>::C1, ClassImpl2<float, N2>::C3, 16}, \
      &ClassImpl2<float, N2>::pass1, &ClassImpl2<float, N2>::pass2, &ClassImpl2<float, N2>::pass3}
@@ -30,9 +30,9 @@ static const ClassKernels kClasses32[] = {
     PA_CLASS2(24, 2048),
 };
 
-const ClassKernels* class_kernels32(int logL) {
+const ClassKernels* class_kernels32(int cls) {
     for (const ClassKernels& k : kClasses32)
-        if (k.cfg.logL == logL) return &k;
+        if (k.cfg.cls == cls) return &k;
     return nullptr;
 }
 

@@ -8,8 +8,8 @@
 namespace pa {
 
 #define PA_CLASS(LOGL, N1, N2) \
-    {ClassCfg{64, LOGL, N1, N2, 4, 8, 16}, &ClassImpl<double, N1, N2, 4, 8, 16>::pass1, \
-     &ClassImpl<double, N1, N2, 4, 8, 16>::pass2, &ClassImpl<double, N1, N2, 4, 8, 16>::pass3}
+    {ClassCfg{64, LOGL, N1, N2, 4, 8, 16}, &ClassImpl<double, N1, N2, 4, 8, 16, 16>::pass1, \
+     &ClassImpl<double, N1, N2, 4, 8, 16, 16>::pass2, &ClassImpl<double, N1, N2, 4, 8, 16, 16>::pass3}
 #define PA_CLASS2(LOGL, N2) \
     {ClassCfg{64, LOGL, kN1, N2, ClassImpl2<double, N2>::C1, ClassImpl2<double, N2>::C3, 16}, \
      &ClassImpl2<double, N2>::pass1, &ClassImpl2<double, N2>::pass2, &ClassImpl2<double, N2>::pass3}
@@ -30,9 +30,9 @@ static const ClassKernels kClasses64[] = {
     PA_CLASS2(24, 2048),
 };
 
-const ClassKernels* class_kernels64(int logL) {
+const ClassKernels* class_kernels64(int cls) {
     for (const ClassKernels& k : kClasses64)
-        if (k.cfg.logL == logL) return &k;
+        if (k.cfg.cls == cls) return &k;
     return nullptr;
 }
 

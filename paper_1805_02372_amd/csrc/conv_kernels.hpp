@@ -101,12 +101,13 @@ __device__ __forceinline__ cx<T> four_step_root(const cx<T>* __restrict__ fa, co
 template <int A, int B> constexpr int cmax() { return A > B ? A : B; }
 
 // ------------------------------------------------------------------ pass 1
-template <typename T, int N1, int N2, int B, int R>
+// NT2: length of the root table tw of the column transforms (a multiple of N2).
+template <typename T, int N1, int N2, int B, int R, int NT2>
 __global__ void __launch_bounds__(B * (N2 / R))
 k_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part,
         const cx<T>* __restrict__ tw, const cx<T>* __restrict__ fa, const cx<T>* __restrict__ fb, int fshift) {
     constexpr uint32_t L = (uint32_t)N1 * N2;
-    constexpr int NCB = N1 / B, NR = N2 / R, NT = cmax<N1, N2>();
+    constexpr int NCB = N1 / B, NR = N2 / R, NT = NT2;
     __shared__ cx<T> lds[lds_slots<N2, B>()];
     __shared__ uint32_t wsum;
 
@@ -188,17 +189,18 @@ __device__ __forceinline__ void mirror(cx<T> (&b)[R], cx<T>* lds, int j) {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const int k1 = j + i * NR;
-        const int src = ZERO ? ((N1 - k1) & (N1 - 1)) : (N1 - 1 - k1);
+        const int src = ZERO ? ((N1 - k1) % N1) : (N1 - 1 - k1);
         b[i] = lds[lds_slot<1>(src, 0)];
     }
 }
 
-template <typename T, int N1, int N2, int R, int NCB1>
+// NT1: length of the root table tw of the row transforms (a multiple of N1).
+template <typename T, int N1, int N2, int R, int NCB1, int NT1>
 __global__ void __launch_bounds__(N1 / R)
 k_pass2(JobTable jt, cx<T>* __restrict__ ws, const uint32_t* __restrict__ part, TileMeta* __restrict__ meta,
         const cx<T>* __restrict__ tw, const cx<T>* __restrict__ fa, const cx<T>* __restrict__ fb, int fshift) {
     constexpr uint32_t L = (uint32_t)N1 * N2;
-    constexpr int NR = N1 / R, NP = N2 / 2, NT = cmax<N1, N2>();
+    constexpr int NR = N1 / R, NP = N2 / 2, NT = NT1;
     __shared__ cx<T> lds[lds_slots<N1, 1>()];
     __shared__ uint32_t wsum;
 
@@ -276,11 +278,15 @@ template <typename T> __device__ __forceinline__ T round_even(T z);
 template <> __device__ __forceinline__ float round_even<float>(float z) { return rintf(z); }
 template <> __device__ __forceinline__ double round_even<double>(double z) { return rint(z); }
 
-template <typename T, int N1, int N2, int B, int R>
+// NT2: length of the root table tw of the column transforms (a multiple of N2).
+// SPLIT: the real rows 0 and n2/2 of V are in the real parts of rows 0 and
+// n2/2 (the layout of the wave-level row pass, conv_v2.hpp) instead of sharing
+// row 0 as re / im.
+template <typename T, int N1, int N2, int B, int R, int NT2, bool SPLIT = false>
 __global__ void __launch_bounds__(B * (N2 / 2 / R))
 k_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta, const cx<T>* __restrict__ tw) {
     constexpr uint32_t L = (uint32_t)N1 * N2;
-    constexpr int N2h = N2 / 2, NR = N2h / R, NCB = N1 / B, NT = cmax<N1, N2>();
+    constexpr int N2h = N2 / 2, NR = N2h / R, NCB = N1 / B, NT = NT2;
     static_assert(64 % B == 0, "column groups must tile a wavefront");
     __shared__ cx<T> lds[lds_slots<N2h, B>()];
     __shared__ uint32_t s_res, s_abs, s_bad;
@@ -297,7 +303,7 @@ k_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta, 
     const int64_t weight = (int64_t)meta[t].popcnt;
 
     // Hermitian column H[k] = V[k][t1] (k < n2/2), H[n2/2] in the imaginary
-    // part of row 0.  U[k] = E[k] + i O[k] with E = H[k] + conj H[n2/2-k],
+    // part of row 0 (SPLIT: the real part of row n2/2).  U[k] = E[k] + i O[k] with E = H[k] + conj H[n2/2-k],
     // O = (H[k] - conj H[n2/2-k]) w_n2^{-k}.
     cx<T> v[R];
 #pragma unroll
@@ -305,7 +311,8 @@ k_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta, 
         const int k = j + i * NR;
         const cx<T> h = V[(size_t)k * N1 + t1];
         if (k == 0) {
-            v[i] = cx<T>{h.re + h.im, h.re - h.im};
+            const T hh = SPLIT ? V[(size_t)N2h * N1 + t1].re : h.im;   // H[n2/2]
+            v[i] = cx<T>{h.re + hh, h.re - hh};
         } else {
             const cx<T> hm = conj(V[(size_t)(N2h - k) * N1 + t1]);
             const cx<T> e = h + hm;
@@ -354,27 +361,32 @@ k_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta, 
     }
 }
 
-template <typename T, int N1, int N2, int B1, int B3, int R>
+// Launchers of one class.  RR / RC: points per thread of the row / column
+// transforms.  SMOOTH: a mixed-radix class, whose row and column transforms
+// take their roots from separate tables of exactly N1 (tw) and N2 (tw2)
+// entries; a power-of-two class uses one table of max(N1, N2) roots for both.
+template <typename T, int N1, int N2, int B1, int B3, int RR, int RC, bool SMOOTH = false>
 struct ClassImpl {
     static constexpr uint32_t L = (uint32_t)N1 * N2;
+    static constexpr int NT1 = SMOOTH ? N1 : cmax<N1, N2>(), NT2 = SMOOTH ? N2 : cmax<N1, N2>();
     static int pass1(const JobTable& jt, void* ws, uint32_t* part, TileMeta*, const Tables& tb, void* stream) {
-        dim3 grid(jt.ntiles * (N1 / B1)), block(B1 * (N2 / R));
-        hipLaunchKernelGGL((k_pass1<T, N1, N2, B1, R>), grid, block, 0, (hipStream_t)stream, jt,
-                           (cx<T>*)ws, part, (const cx<T>*)tb.tw, (const cx<T>*)tb.fa, (const cx<T>*)tb.fb,
+        dim3 grid(jt.ntiles * (N1 / B1)), block(B1 * (N2 / RC));
+        hipLaunchKernelGGL((k_pass1<T, N1, N2, B1, RC, NT2>), grid, block, 0, (hipStream_t)stream, jt,
+                           (cx<T>*)ws, part, (const cx<T>*)tb.tw2, (const cx<T>*)tb.fa, (const cx<T>*)tb.fb,
                            tb.fshift);
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
     static int pass2(const JobTable& jt, void* ws, uint32_t* part, TileMeta* meta, const Tables& tb, void* stream) {
-        dim3 grid(jt.ntiles * (N2 / 2)), block(N1 / R);
-        hipLaunchKernelGGL((k_pass2<T, N1, N2, R, N1 / B1>), grid, block, 0, (hipStream_t)stream, jt,
+        dim3 grid(jt.ntiles * (N2 / 2)), block(N1 / RR);
+        hipLaunchKernelGGL((k_pass2<T, N1, N2, RR, N1 / B1, NT1>), grid, block, 0, (hipStream_t)stream, jt,
                            (cx<T>*)ws, (const uint32_t*)part, meta, (const cx<T>*)tb.tw, (const cx<T>*)tb.fa,
                            (const cx<T>*)tb.fb, tb.fshift);
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
     static int pass3(const JobTable& jt, void* ws, uint32_t*, TileMeta* meta, const Tables& tb, void* stream) {
-        dim3 grid(jt.ntiles * (N1 / B3)), block(B3 * (N2 / 2 / R));
-        hipLaunchKernelGGL((k_pass3<T, N1, N2, B3, R>), grid, block, 0, (hipStream_t)stream, jt,
-                           (const cx<T>*)ws, meta, (const cx<T>*)tb.tw);
+        dim3 grid(jt.ntiles * (N1 / B3)), block(B3 * (N2 / 2 / RC));
+        hipLaunchKernelGGL((k_pass3<T, N1, N2, B3, RC, NT2>), grid, block, 0, (hipStream_t)stream, jt,
+                           (const cx<T>*)ws, meta, (const cx<T>*)tb.tw2);
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
 };

@@ -691,4 +691,34 @@ struct ClassImpl2 {
     }
 };
 
+// Mixed-radix classes with rows of 8192 (L = 8192 n2, n2 = P 2^b): the
+// wave-level row pass above (it does not depend on how n2 factors) between
+// the workgroup-wide Stockham column passes of conv_kernels.hpp, whose columns
+// carry the radix-P stage (RC points per thread).
+template <typename T, int N2, int B1, int B3, int RC>
+struct ClassImplS {
+    static constexpr int NCB1 = kN1 / B1;
+    static int pass1(const JobTable& jt, void* ws, uint32_t* part, TileMeta*, const Tables& tb, void* stream) {
+        dim3 grid(jt.ntiles * NCB1), block(B1 * (N2 / RC));
+        hipLaunchKernelGGL((k_pass1<T, kN1, N2, B1, RC, N2>), grid, block, 0, (hipStream_t)stream, jt, (cx<T>*)ws,
+                           part, (const cx<T>*)tb.tw2, (const cx<T>*)tb.fa, (const cx<T>*)tb.fb, tb.fshift);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
+    static int pass2(const JobTable& jt, void* ws, uint32_t* part, TileMeta* meta, const Tables& tb, void* stream) {
+        const uint32_t units = jt.ntiles * (N2 / 2);
+        const uint32_t wgs = kRowPersistent<T> ? (uint32_t)row_pass_workgroups() : units;
+        dim3 grid(units < wgs ? units : wgs), block(512);
+        hipLaunchKernelGGL((k2_pass2<T, N2, NCB1>), grid, block, 0, (hipStream_t)stream, jt, (cx<T>*)ws,
+                           (const uint32_t*)part, meta, (const cx<T>*)tb.tw, (const cx<T>*)tb.stw,
+                           (const cx<double>*)tb.fa64, (const cx<double>*)tb.fb64, tb.fshift);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
+    static int pass3(const JobTable& jt, void* ws, uint32_t*, TileMeta* meta, const Tables& tb, void* stream) {
+        dim3 grid(jt.ntiles * (kN1 / B3)), block(B3 * (N2 / 2 / RC));
+        hipLaunchKernelGGL((k_pass3<T, kN1, N2, B3, RC, N2, true>), grid, block, 0, (hipStream_t)stream, jt,
+                           (const cx<T>*)ws, meta, (const cx<T>*)tb.tw2);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
+};
+
 }  // namespace pa

@@ -104,7 +104,7 @@ void HostBuf::release() {
 // ------------------------------------------------------------ twiddle tables
 
 bool Ctx::plan_cached(uint64_t n, uint64_t m, int policy, TilePlan* out) {
-    const auto key = std::make_tuple(n, m, policy, min_logL(policy), max_logL(policy));
+    const auto key = std::make_tuple(n, m, policy, class_filter_key());
     {
         std::lock_guard<std::mutex> lk(plan_mu);
         auto it = plans.find(key);
@@ -125,65 +125,70 @@ bool Ctx::plan_cached(uint64_t n, uint64_t m, int policy, TilePlan* out) {
     return true;
 }
 
-pa_status table_image(int prec, int logL, std::vector<unsigned char>* host, size_t off[6], int* fshift) {
+pa_status table_image(int prec, int cls, std::vector<unsigned char>* host, size_t off[kTableSections],
+                      int* fshift) {
     ClassGeom g;
-    if (!class_geometry(prec, logL, &g)) return PA_EINVAL;
+    if (!class_geometry(prec, cls, &g)) return PA_EINVAL;
     auto pack = [&](auto& th) {
         using E = typename std::remove_reference<decltype(th.tw)>::type::value_type;
-        const void* src[6] = {th.tw.data(), th.fa.data(), th.fb.data(), th.stw.data(), th.fa64.data(),
-                              th.fb64.data()};
-        const size_t bytes[6] = {th.tw.size() * sizeof(E), th.fa.size() * sizeof(E), th.fb.size() * sizeof(E),
-                                 th.stw.size() * sizeof(E), th.fa64.size() * sizeof(double),
-                                 th.fb64.size() * sizeof(double)};
+        const void* src[kTableSections] = {th.tw.data(),  th.tw2.data(),  th.fa.data(), th.fb.data(),
+                                           th.stw.data(), th.fa64.data(), th.fb64.data()};
+        const size_t bytes[kTableSections] = {th.tw.size() * sizeof(E),   th.tw2.size() * sizeof(E),
+                                              th.fa.size() * sizeof(E),   th.fb.size() * sizeof(E),
+                                              th.stw.size() * sizeof(E),  th.fa64.size() * sizeof(double),
+                                              th.fb64.size() * sizeof(double)};
         size_t total = 0;
-        for (int k = 0; k < 6; ++k) {
-            off[k] = total;
+        for (int k = 0; k < kTableSections; ++k) {
+            off[k] = bytes[k] ? total : ~(size_t)0;   // ~0: section absent
             total += (bytes[k] + 255) & ~(size_t)255;
         }
         host->assign(total, 0);
-        for (int k = 0; k < 6; ++k)
+        for (int k = 0; k < kTableSections; ++k)
             if (bytes[k]) memcpy(host->data() + off[k], src[k], bytes[k]);
         *fshift = th.fshift;
     };
+    const bool smooth = cls >= 32;
     if (prec == PREC_NTT) {
         TableHost<uint32_t> th;
-        build_ntt_tables(logL, g.n1, g.n2, &th);
+        build_ntt_tables(g.L, g.n1, g.n2, &th);
         pack(th);
     } else if (prec == PREC_FP32) {
         TableHost<float> th;
-        build_tables<float>(logL, g.n1, g.n2, &th);
+        build_tables<float>(g.L, g.n1, g.n2, smooth, &th);
         pack(th);
     } else {
         TableHost<double> th;
-        build_tables<double>(logL, g.n1, g.n2, &th);
+        build_tables<double>(g.L, g.n1, g.n2, smooth, &th);
         pack(th);
     }
     return PA_OK;
 }
 
-Tables table_view(int prec, unsigned char* base, const size_t off[6], int fshift) {
+Tables table_view(int prec, unsigned char* base, const size_t off[kTableSections], int fshift) {
+    auto at = [&](int k) -> const void* { return off[k] == ~(size_t)0 ? nullptr : base + off[k]; };
     Tables t;
     t.fshift = fshift;
-    t.tw = base + off[0];
-    t.fa = base + off[1];
-    t.fb = base + off[2];
-    t.stw = base + off[3];
+    t.tw = at(0);
+    t.tw2 = at(1) ? at(1) : t.tw;   // power-of-two classes: one table for rows and columns
+    t.fa = at(2);
+    t.fb = at(3);
+    t.stw = at(4);
     // an FP32 class carries its own FP64 two-level tables; an FP64 class uses fa, fb
     const bool own64 = prec == PREC_FP32;
-    t.fa64 = (const double*)(own64 ? base + off[4] : base + off[1]);
-    t.fb64 = (const double*)(own64 ? base + off[5] : base + off[2]);
+    t.fa64 = (const double*)(own64 ? at(5) : at(2));
+    t.fb64 = (const double*)(own64 ? at(6) : at(3));
     return t;
 }
 
-pa_status Ctx::tables(int prec, int logL, Tables* out) {
+pa_status Ctx::tables(int prec, int cls, Tables* out) {
     std::lock_guard<std::mutex> lk(tab_mu);
-    const int key = prec * 100 + logL;
+    const int key = prec * 100 + cls;
     auto it = tabs.find(key);
     if (it == tabs.end()) {
         std::vector<unsigned char> host;
-        size_t off[6];
+        size_t off[kTableSections];
         int fshift = 0;
-        pa_status st = table_image(prec, logL, &host, off, &fshift);
+        pa_status st = table_image(prec, cls, &host, off, &fshift);
         if (st != PA_OK) return st;
         DevTables dt;
         st = dt.buf.ensure(this, host.size());
@@ -197,8 +202,8 @@ pa_status Ctx::tables(int prec, int logL, Tables* out) {
     return PA_OK;
 }
 
-pa_status lane_tables(Ctx* c, const Lane& ln, int prec, int logL, Tables* out) {
-    return ln.static_tables ? noalloc_tables(c->device, prec, logL, out) : c->tables(prec, logL, out);
+pa_status lane_tables(Ctx* c, const Lane& ln, int prec, int cls, Tables* out) {
+    return ln.static_tables ? noalloc_tables(c->device, prec, cls, out) : c->tables(prec, cls, out);
 }
 
 // ------------------------------------------------------------ pass timing
@@ -282,12 +287,12 @@ static pa_status run_passes(const ClassKernels* K, JobTable jt, uint32_t first, 
     return PA_OK;
 }
 
-pa_status Lane::launch(Ctx* c, int prec_, int logL_, std::vector<JobDesc>& js, bool timing, bool fetch_meta,
+pa_status Lane::launch(Ctx* c, int prec_, int cls_, std::vector<JobDesc>& js, bool timing, bool fetch_meta,
                        pa_stats* stats) {
-    const ClassKernels* K = class_kernels(prec_, logL_);
+    const ClassKernels* K = class_kernels(prec_, cls_);
     if (!K || js.empty()) return PA_EINVAL;
     prec = prec_;
-    logL = logL_;
+    cls = cls_;
     const ClassCfg& cfg = K->cfg;
     // Tiles in job order; within a job chunk 0 comes first, so a window is
     // cleared (pass 1 of its chunk-0 tile) before any chunk XORs into it, also
@@ -298,7 +303,7 @@ pa_status Lane::launch(Ctx* c, int prec_, int logL_, std::vector<JobDesc>& js, b
         total += jd.nchunks * jd.nouts;
     }
     Tables tb;
-    pa_status st = lane_tables(c, *this, prec, logL, &tb);
+    pa_status st = lane_tables(c, *this, prec, cls, &tb);
     if (st != PA_OK) return st;
     st = meta.ensure(c, (size_t)total * sizeof(TileMeta), stream);
     if (st != PA_OK) return st;
@@ -312,7 +317,7 @@ pa_status Lane::launch(Ctx* c, int prec_, int logL_, std::vector<JobDesc>& js, b
     // tiles per launch: as many as the budget (and the lane cap) allows; on a
     // failed allocation halve until one tile
     const size_t elt = cfg.prec == 64 ? 16 : 8;
-    const size_t tile_bytes = ((size_t)1 << cfg.logL) * elt;
+    const size_t tile_bytes = (size_t)class_len(cfg.cls) * elt;
     const size_t part_bytes = (size_t)(cfg.n1 / cfg.b1) * sizeof(uint32_t);
     size_t G = total;
     if (ws.fixed) {   // a fixed workspace: as many tiles as it holds
@@ -407,7 +412,7 @@ pa_status Lane::finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_s
         }
         return lo;
     };
-    const ClassKernels* K64 = class_kernels(PREC_FP64, logL);
+    const ClassKernels* K64 = class_kernels(PREC_FP64, cls);
     if (prec != PREC_FP32 || (flags & PA_NO_FALLBACK) || !K64) {
         if (per_job)
             for (uint32_t t : failed) (*per_job)[job_of(t)] = PA_EPRECISION;
@@ -421,12 +426,12 @@ pa_status Lane::finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_s
     //    first run's.  If the repeat's certificate is not bit-identical to the
     //    first run's, the whole job is rebuilt in FP64 instead (its windows
     //    cleared and rebuilt).
-    const ClassKernels* K32 = class_kernels(PREC_FP32, logL);
+    const ClassKernels* K32 = class_kernels(PREC_FP32, cls);
     Tables tb, tb32;
-    pa_status st = lane_tables(c, *this, PREC_FP64, logL, &tb);
-    if (st == PA_OK) st = lane_tables(c, *this, PREC_FP32, logL, &tb32);
+    pa_status st = lane_tables(c, *this, PREC_FP64, cls, &tb);
+    if (st == PA_OK) st = lane_tables(c, *this, PREC_FP32, cls, &tb32);
     if (st != PA_OK) return st;
-    st = ws.ensure(c, ((size_t)1 << logL) * 16, stream);
+    st = ws.ensure(c, (size_t)class_len(cls) * 16, stream);
     if (st != PA_OK) return st;
     const size_t part_words = std::max<size_t>(K64->cfg.n1 / K64->cfg.b1, K32 ? K32->cfg.n1 / K32->cfg.b1 : 0);
     st = part.ensure(c, part_words * sizeof(uint32_t), stream);
@@ -533,9 +538,10 @@ uint32_t prec_flag(int prec) {
 
 void fill_plan_stats(pa_stats* s, const TilePlan& p) {
     ClassGeom g;
-    class_geometry(p.prec, p.logL, &g);
+    class_geometry(p.prec, p.cls, &g);
     s->prec = prec_flag(p.prec);
-    s->log2_len = (uint32_t)p.logL;
+    s->log2_len = (uint32_t)ceil_log2(p.L);
+    s->fft_len = (uint32_t)p.L;
     s->n1 = (uint32_t)g.n1;
     s->n2 = (uint32_t)g.n2;
     s->chunk_bits = p.Bi;
@@ -543,7 +549,7 @@ void fill_plan_stats(pa_stats* s, const TilePlan& p) {
     s->bound = std::max(s->bound, p.bound);
     s->rigorous_bound = std::max(s->rigorous_bound, p.rigorous);
     if (p.prec == PREC_FP32 || p.prec == PREC_FP64) s->certified = PA_CERT_A_PRIORI;   // settled by set_certified
-    s->model_bytes += p.tiles() * ((p.prec == PREC_FP64 ? 48ull : 24ull) << p.logL);
+    s->model_bytes += p.tiles() * (p.prec == PREC_FP64 ? 48ull : 24ull) * p.L;
 }
 
 void set_certified(pa_stats* s, pa_status st) {
@@ -666,7 +672,7 @@ pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, con
         // NTT) may skip the certificate read-back; kernel timing needs the
         // launch to finish.
         const bool async = dev && (flags & PA_ASYNC) && plan.rigorous < kRigorousLimit && !timing;
-        s = ln.launch(c, plan.prec, plan.logL, jobs, timing, !async, &st);
+        s = ln.launch(c, plan.prec, plan.cls, jobs, timing, !async, &st);
         if (s == PA_OK && !async) s = ln.finish(c, flags, &st, nullptr);
     }
     if (s == PA_OK && !dev) {
@@ -839,7 +845,7 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
             const BatchGroup& g = groups[queue.front()];
             std::vector<JobDesc> jobs(g.jobs.size());
             for (size_t q = 0; q < g.jobs.size(); ++q) jobs[q] = all[g.jobs[q]];
-            const pa_status ls = lanes[k]->launch(c, g.plans[0].prec, g.logL, jobs, flags & PA_TIMING, true, &lst[k]);
+            const pa_status ls = lanes[k]->launch(c, g.plans[0].prec, g.cls, jobs, flags & PA_TIMING, true, &lst[k]);
             if (ls != PA_OK) {
                 for (size_t q = 0; q < g.jobs.size(); ++q) status[g.jobs[q]] = ls;
                 s = ls;
@@ -910,9 +916,10 @@ pa_status pa_plan_query(uint64_t n, uint64_t m, uint32_t flags, pa_plan* out) {
     TilePlan p;
     if (!plan_job(n, m, policy, cm, &p)) return PA_EINVAL;
     ClassGeom g;
-    class_geometry(p.prec, p.logL, &g);
+    class_geometry(p.prec, p.cls, &g);
     out->prec = prec_flag(p.prec);
-    out->log2_len = (uint32_t)p.logL;
+    out->log2_len = (uint32_t)ceil_log2(p.L);
+    out->fft_len = (uint32_t)p.L;
     out->n1 = (uint32_t)g.n1;
     out->n2 = (uint32_t)g.n2;
     out->chunk_bits = p.Bi;
@@ -923,7 +930,6 @@ pa_status pa_plan_query(uint64_t n, uint64_t m, uint32_t flags, pa_plan* out) {
     out->cost = p.cost;
     out->direct_cost = direct_cost(n, m, cm);
     out->direct = choose_direct(flags, n, m, cm, p) ? 1u : 0u;
-    out->reserved = 0;
     out->rigorous_bound = p.rigorous;
     return PA_OK;
 }
@@ -977,7 +983,8 @@ double pa_error_model(uint32_t prec, uint32_t log2_len, uint64_t chunk_bits) {
     if ((prec & PA_PREC_MASK) == PA_PREC_DIRECT) return 0.0;   // exact
     const int p = policy_of(prec);
     if (p < 0) return -1.0;
-    return error_bound(p, (int)log2_len, chunk_bits);
+    if (log2_len < 1 || log2_len > 40) return -1.0;
+    return error_bound(p, 1ull << log2_len, chunk_bits);
 }
 
 }  // extern "C"

@@ -72,17 +72,17 @@ struct Lane {
     bool static_tables = false;   // twiddle tables from the no-allocation entry's array
 
     // In-flight state of an asynchronous launch (serving).
-    int prec = 0, logL = 0;
+    int prec = 0, cls = 0;
     uint32_t total_tiles = 0;
     std::vector<JobDesc> jobs;
     hipEvent_t done = nullptr;
 
     void release(Ctx* c);
 
-    // Enqueue every tile of `jobs` (planned at class prec/logL); sets
+    // Enqueue every tile of `jobs` (planned at precision prec, class cls); sets
     // tile_begin.  With `fetch_meta` the tile
     // certificates are copied to meta_host behind the kernels.
-    pa_status launch(Ctx* c, int prec, int logL, std::vector<JobDesc>& jobs, bool timing, bool fetch_meta,
+    pa_status launch(Ctx* c, int prec, int cls, std::vector<JobDesc>& jobs, bool timing, bool fetch_meta,
                      pa_stats* stats);
     // After the launch completed: check certificates, re-run failed FP32
     // tiles (whole jobs when they accumulate chunks) in FP64.  Synchronous on
@@ -118,14 +118,14 @@ struct Ctx {
     std::map<int, DevTables> tabs;
     CostModel cost;
     // Plans of recent single-job shapes (key: n, m, policy and the class
-    // limits in force); cleared when the cost model changes.
+    // filter in force); cleared when the cost model changes.
     std::mutex plan_mu;
-    std::map<std::tuple<uint64_t, uint64_t, int, int, int>, TilePlan> plans;
+    std::map<std::tuple<uint64_t, uint64_t, int, uint64_t>, TilePlan> plans;
     bool plan_cached(uint64_t n, uint64_t m, int policy, TilePlan* out);
     bool pools = false;   // stream-ordered allocation supported on the device
     pa_stats last{};
 
-    pa_status tables(int prec, int logL, Tables* out);
+    pa_status tables(int prec, int cls, Tables* out);
 
     // ---- serving
     std::mutex smu;
@@ -159,18 +159,19 @@ double now_seconds();
 pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path);
 pa_status tune_load(Ctx* c, const char* path);
 
-// Twiddle tables of a length class as one host image: sections tw, fa, fb,
-// stw (element type of the class), fa64, fb64 (FP64), each on a 256-byte
-// boundary; `off` receives the section offsets.
-pa_status table_image(int prec, int logL, std::vector<unsigned char>* host, size_t off[6], int* fshift);
+// Twiddle tables of a length class as one host image: sections tw, tw2, fa,
+// fb, stw (element type of the class), fa64, fb64 (FP64), each on a 256-byte
+// boundary; `off` receives the section offsets (~0 for an empty section).
+constexpr int kTableSections = 7;
+pa_status table_image(int prec, int cls, std::vector<unsigned char>* host, size_t off[kTableSections], int* fshift);
 // Device pointers of the sections of an image copied to `base`.
-Tables table_view(int prec, unsigned char* base, const size_t off[6], int fshift);
+Tables table_view(int prec, unsigned char* base, const size_t off[kTableSections], int fshift);
 // Tables of a class for a lane: the context's cache, or the no-allocation
 // entry's array (Lane::static_tables).
-pa_status lane_tables(Ctx* c, const Lane& ln, int prec, int logL, Tables* out);
+pa_status lane_tables(Ctx* c, const Lane& ln, int prec, int cls, Tables* out);
 // No-allocation entry: per-device set-up (called by pa_create with the device
 // current) and its tables.
 pa_status noalloc_setup(int device);
-pa_status noalloc_tables(int device, int prec, int logL, Tables* out);
+pa_status noalloc_tables(int device, int prec, int cls, Tables* out);
 
 }  // namespace pa

@@ -1,6 +1,6 @@
 // Device-side FFT building blocks for gfx950: complex arithmetic, radix
-// 2/4/8/16 DFT butterflies in registers, and a Stockham auto-sort FFT whose
-// stages exchange data through LDS.
+// 2/3/4/5/7/8/16 DFT butterflies in registers, and a mixed-radix Stockham
+// auto-sort FFT whose stages exchange data through LDS.
 //
 // Conventions.  DIR = -1 is the forward transform X_k = sum_t x_t w^{tk} with
 // w = exp(-2 pi i / N); DIR = +1 the unnormalised inverse (w -> conj w).
@@ -8,7 +8,8 @@
 // precision, computed on the host in extended precision; a DIR = +1 stage uses
 // their conjugates.
 //
-// Stockham stage (radix Rs, span Ns, N points): butterfly q reads
+// Stockham stage (radix Rs, span Ns = product of the earlier radices, N
+// points; any factorisation of N into the radices above): butterfly q reads
 // x[q + r N/Rs] (r < Rs), multiplies input r by w_{Ns Rs}^{(q mod Ns) r},
 // applies the Rs-point DFT and writes output s to
 // x'[(q / Ns) Ns Rs + (q mod Ns) + s Ns].  After the last stage (Ns Rs = N) the
@@ -143,9 +144,62 @@ template <int DIR, typename T> __device__ __forceinline__ void dft16(cx<T>* u) {
     t = u[11]; u[11] = u[14]; u[14] = t;
 }
 
+// cos and sin of 2 pi e / P (0 < e <= P/2) for the odd radices P = 3, 5, 7
+// (double literals; rounded once to the working precision where used).
+constexpr double odd_root(int P, int e, bool sine) {
+    if (P == 3) return sine ? 0.86602540378443864676372317075294 : -0.5;
+    if (P == 5) {
+        if (e == 1) return sine ? 0.95105651629515357211643933337938 : 0.30901699437494742410229341718282;
+        return sine ? 0.58778525229247312916870595463907 : -0.80901699437494742410229341718282;
+    }
+    if (e == 1) return sine ? 0.78183148246802980870844452667406 : 0.62348980185873353052500488400424;
+    if (e == 2) return sine ? 0.97492791218182360701813168299393 : -0.22252093395631440428890256449679;
+    return sine ? 0.43388373911755812047576833284836 : -0.90096886790241912623610231950745;
+}
+// cos(2 pi e / P) and sin(2 pi e / P) for any 0 < e < P
+constexpr double odd_cos(int P, int e) { return odd_root(P, e <= P / 2 ? e : P - e, false); }
+constexpr double odd_sin(int P, int e) { return e <= P / 2 ? odd_root(P, e, true) : -odd_root(P, P - e, true); }
+
+// P-point DFT for an odd prime P by pairing inputs s and P - s: with
+// a_s = u_s + u_{P-s} and b_s = u_s - u_{P-s} (s = 1 .. (P-1)/2),
+//   y_k     = u_0 + sum_s cos(2 pi s k / P) a_s + DIR i sum_s sin(2 pi s k / P) b_s,
+//   y_{P-k} = the same with the sine sum negated   (k = 1 .. (P-1)/2),
+// since the root of the transform is exp(DIR 2 pi i / P).  All loops unroll,
+// so the roots are compile-time constants.
+template <int DIR, int P, typename T> __device__ __forceinline__ void dft_odd(cx<T>* u) {
+    constexpr int H = (P - 1) / 2;
+    cx<T> a[H], b[H];
+#pragma unroll
+    for (int s = 0; s < H; ++s) {
+        a[s] = u[s + 1] + u[P - 1 - s];
+        b[s] = u[s + 1] - u[P - 1 - s];
+    }
+    const cx<T> u0 = u[0];
+    cx<T> y0 = u0;
+#pragma unroll
+    for (int s = 0; s < H; ++s) y0 = y0 + a[s];
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+        cx<T> c = u0, d = cx<T>{T(0), T(0)};
+#pragma unroll
+        for (int s = 1; s <= H; ++s) {
+            const T cs = (T)odd_cos(P, (s * k) % P), sn = (T)odd_sin(P, (s * k) % P);
+            c.re += cs * a[s - 1].re;
+            c.im += cs * a[s - 1].im;
+            d.re += sn * b[s - 1].re;
+            d.im += sn * b[s - 1].im;
+        }
+        const cx<T> id = rot90<DIR>(d);   // DIR i d
+        u[k] = c + id;
+        u[P - k] = c - id;
+    }
+    u[0] = y0;
+}
+
 template <int Rs, int DIR, typename T> __device__ __forceinline__ void dft(cx<T>* u) {
     if constexpr (Rs == 1) {
     } else if constexpr (Rs == 2) dft2<DIR>(u[0], u[1]);
+    else if constexpr (Rs == 3 || Rs == 5 || Rs == 7) dft_odd<DIR, Rs>(u);
     else if constexpr (Rs == 4) dft4<DIR>(u[0], u[1], u[2], u[3]);
     else if constexpr (Rs == 8) dft8<DIR>(u);
     else if constexpr (Rs == 16) dft16<DIR>(u);
@@ -164,11 +218,23 @@ template <int N, int F> constexpr int lds_slots() { return N * F + (N * F >> 4) 
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
-// Radix of the first stage: makes the remaining length a power of R.
-template <int N, int R> constexpr int first_radix() {
-    int k = ilog2(N), r = ilog2(R);
-    int rem = k % r;
-    return rem ? (1 << rem) : R;
+// Stage radices of an N-point transform whose threads hold R points each.
+// N = P * 2^k with P in {1, 3, 5, 7} dividing R: an odd first stage of radix
+// P, then power-of-two stages of radix Q (the largest power of two dividing
+// R, at most 16), the first of them taking the remainder so that the rest are
+// all radix Q.
+constexpr int odd_part(int n) { return (n % 2 == 0 && n > 0) ? odd_part(n / 2) : n; }
+constexpr int pow2_radix(int R, int q = 1) { return (R % (2 * q) == 0 && 2 * q <= 16) ? pow2_radix(R, 2 * q) : q; }
+constexpr int stockham_radix(int N, int R, int Ns) {
+    const int P = odd_part(N);
+    if (Ns == 1 && P > 1) return P;
+    const int lq = ilog2(pow2_radix(R)), lr = ilog2(N / Ns);
+    return (Ns == P && lr % lq) ? (1 << (lr % lq)) : (1 << lq);
+}
+// Whether the FFT below supports (N, R).
+constexpr bool stockham_ok(int N, int R) {
+    const int P = odd_part(N);
+    return N % R == 0 && (P == 1 || P == 3 || P == 5 || P == 7) && R % P == 0 && pow2_radix(R) >= 2;
 }
 
 // One Stockham stage.  v: the thread's R points (layout described above).
@@ -185,7 +251,8 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[R], cx<T>* lds, int j,
 #pragma unroll
         for (int r = 0; r < Rs; ++r) u[r] = v[p + r * P];
         if constexpr (Ns > 1) {
-            const int k = (j + p * NR) & (Ns - 1);
+            const int k = (j + p * NR) % Ns;
+            static_assert(NT % (Ns * Rs) == 0, "twiddle table length");
             constexpr int step = NT / (Ns * Rs);
 #pragma unroll
             for (int r = 1; r < Rs; ++r) u[r] = twmul<DIR>(u[r], tw[k * r * step]);
@@ -199,7 +266,7 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[R], cx<T>* lds, int j,
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const int q = j + p * NR;
-            const int k = q & (Ns - 1);
+            const int k = q % Ns;
             const int base = (q / Ns) * Ns * Rs + k;
 #pragma unroll
             for (int r = 0; r < Rs; ++r) lds[lds_slot<F>(base + r * Ns, f)] = v[p + r * P];
@@ -210,14 +277,11 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[R], cx<T>* lds, int j,
     }
 }
 
-// Stage radices: at most 16; the first stage takes the remainder so that the
-// others are all radix min(R, 16).
-template <int R> constexpr int stage_radix() { return R > 16 ? 16 : R; }
-
 template <typename T, int DIR, int N, int R, int F, int NT, int Ns>
 __device__ __forceinline__ void fft_stages(cx<T> (&v)[R], cx<T>* lds, int j, int f,
                                            const cx<T>* __restrict__ tw) {
-    constexpr int Rs = (Ns == 1) ? first_radix<N, stage_radix<R>()>() : stage_radix<R>();
+    constexpr int Rs = stockham_radix(N, R, Ns);
+    static_assert(R % Rs == 0, "stage radix divides the points per thread");
     stockham_stage<T, DIR, N, R, Rs, Ns, F, NT>(v, lds, j, f, tw);
     if constexpr (Ns * Rs < N) fft_stages<T, DIR, N, R, F, NT, Ns * Rs>(v, lds, j, f, tw);
 }
@@ -229,7 +293,7 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[R], cx<T>* lds, int j, int
 template <typename T, int DIR, int N, int R, int F, int NT>
 __device__ __forceinline__ void fft(cx<T> (&v)[R], cx<T>* lds, int j, int f,
                                     const cx<T>* __restrict__ tw) {
-    static_assert((N & (N - 1)) == 0 && N >= R && R >= 2, "power-of-two N >= R");
+    static_assert(stockham_ok(N, R), "N = P 2^k (P = 1, 3, 5, 7), R a multiple of P and of 2");
     fft_stages<T, DIR, N, R, F, NT, 1>(v, lds, j, f, tw);
 }
 

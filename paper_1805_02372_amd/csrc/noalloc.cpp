@@ -42,7 +42,7 @@ namespace pa {
 namespace {
 
 struct TabSlot {
-    int prec = 0, logL = 0;   // class held (prec 0: empty)
+    int prec = 0, cls = 0;    // class held (prec 0: empty)
     uint64_t used = 0;        // last use (eviction order)
     Tables t{};
 };
@@ -99,16 +99,16 @@ pa_status noalloc_setup(int device) {
     return PA_OK;
 }
 
-// Tables of class (prec, logL) in one of the array's table slots.  The caller
+// Tables of class (prec, cls) in one of the array's table slots.  The caller
 // holds the device's mutex.  A class not held yet is built on the host and
 // copied into the least recently used slot in the order of the lane's stream
 // (after the kernels already queued there).
-pa_status noalloc_tables(int device, int prec, int logL, Tables* out) {
+pa_status noalloc_tables(int device, int prec, int cls, Tables* out) {
     if (device < 0 || device >= kMaxDevices || !g_dev[device].ready) return PA_EDEVICE;
     NoAllocDev& d = g_dev[device];
     TabSlot* victim = &d.slots[0];
     for (TabSlot& s : d.slots) {
-        if (s.prec == prec && s.logL == logL) {
+        if (s.prec == prec && s.cls == cls) {
             s.used = ++d.clock;
             *out = s.t;
             return PA_OK;
@@ -116,9 +116,9 @@ pa_status noalloc_tables(int device, int prec, int logL, Tables* out) {
         if (s.used < victim->used) victim = &s;
     }
     std::vector<unsigned char> host;
-    size_t off[6];
+    size_t off[kTableSections];
     int fshift = 0;
-    pa_status st = table_image(prec, logL, &host, off, &fshift);
+    pa_status st = table_image(prec, cls, &host, off, &fshift);
     if (st != PA_OK) return st;
     if (host.size() > kTabSlotBytes) return PA_ESCRATCH;
     unsigned char* base = d.ptr + kWsBytes + kPartBytes + kMetaBytes + (size_t)(victim - d.slots) * kTabSlotBytes;
@@ -126,7 +126,7 @@ pa_status noalloc_tables(int device, int prec, int logL, Tables* out) {
         hipStreamSynchronize(d.lane.stream) != hipSuccess)
         return PA_EDEVICE;
     victim->prec = prec;
-    victim->logL = logL;
+    victim->cls = cls;
     victim->used = ++d.clock;
     victim->t = table_view(prec, base, off, fshift);
     *out = victim->t;
@@ -177,7 +177,7 @@ extern "C" pa_status pa_hash_noalloc(pa_ctx* ctx, const uint64_t* seed, uint64_t
         std::vector<JobDesc> jobs(1);
         fill_job(&jobs[0], seed, key, out, n, m, plan);
         const bool async = (flags & PA_ASYNC) && plan.rigorous < kRigorousLimit;
-        s = ln.launch(c, plan.prec, plan.logL, jobs, false, !async, &st);
+        s = ln.launch(c, plan.prec, plan.cls, jobs, false, !async, &st);
         if (s == PA_OK && !async) s = ln.finish(c, flags & ~PA_TIMING, &st, nullptr);
     }
     set_certified(&st, s);

@@ -321,7 +321,8 @@ struct Impl {
 
 }  // namespace ntt
 
-// Classes: L = n1 * n2 = 2^logL, n2 = 2^min(11, logL/2), rows up to 8192.
+// Classes (power-of-two only): L = n1 * n2 = 2^logL, n2 = 2^min(11, logL/2),
+// rows up to 8192.
 #define PA_NTT_CLASS(LOGL, N1, N2) \
     {ClassCfg{1, LOGL, N1, N2, ntt::kB1, ntt::kB3, ntt::kR}, &ntt::Impl<N1, N2>::pass1, \
      &ntt::Impl<N1, N2>::pass2, &ntt::Impl<N1, N2>::pass3}
@@ -334,9 +335,9 @@ static const ClassKernels kClassesNtt[] = {
     PA_NTT_CLASS(24, 8192, 2048),
 };
 
-const ClassKernels* class_kernels_ntt(int logL) {
+const ClassKernels* class_kernels_ntt(int cls) {
     for (const ClassKernels& k : kClassesNtt)
-        if (k.cfg.logL == logL) return &k;
+        if (k.cfg.cls == cls) return &k;
     return nullptr;
 }
 

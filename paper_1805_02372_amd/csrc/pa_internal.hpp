@@ -47,10 +47,30 @@ struct TileMeta {
     uint32_t badpar;      // outputs whose rounded value had the wrong parity
 };
 
-// One FFT length class: L = n1 * n2 = 2^logL.
+// FFT length classes.  A class is named by an id: log2 L for the power-of-two
+// classes (ids 12 .. 24, every precision), and 32 + 3 (k - 12) + (P - 3) / 2
+// for the mixed-radix classes L = P 2^k, P = 3, 5, 7, 2^14 < L < 2^24 (FP32
+// and FP64 only; radix-P transform stages, section 3 step 1 pads the product
+// to an arbitrary length).
+constexpr int kMinClassId = 12;
+constexpr int kMaxClassId = 63;
+constexpr int smooth_id(int P, int k) { return 32 + 3 * (k - 12) + (P - 3) / 2; }
+constexpr int smooth_P(int id) { return 3 + 2 * ((id - 32) % 3); }
+constexpr int smooth_k(int id) { return 12 + (id - 32) / 3; }
+constexpr bool smooth_valid(int id) {
+    return id >= 32 && id <= kMaxClassId && ((uint64_t)smooth_P(id) << smooth_k(id)) > (1ull << 14) &&
+           ((uint64_t)smooth_P(id) << smooth_k(id)) < (1ull << 24);
+}
+constexpr bool class_id_valid(int id) { return (id >= 12 && id <= 24) || smooth_valid(id); }
+// FFT length of a class id (0 if none).
+constexpr uint64_t class_len(int id) {
+    return (id >= 12 && id <= 24) ? (1ull << id) : smooth_valid(id) ? ((uint64_t)smooth_P(id) << smooth_k(id)) : 0;
+}
+
+// One FFT length class: L = n1 * n2.
 struct ClassCfg {
-    int prec;             // 32 or 64
-    int logL;
+    int prec;             // 32 or 64 (1: NTT)
+    int cls;              // class id (above)
     int n1, n2;           // row length (pass 2), column length (pass 1/3)
     int b1, b3;           // columns per workgroup in pass 1 / pass 3
     int r;                // points per thread
@@ -58,8 +78,10 @@ struct ClassCfg {
 
 // Device pointers of a class's twiddle tables (element type matches prec).
 struct Tables {
-    const void* tw;       // w_NT^e, e < NT = max(n1, n2)
-    const void* fa;       // w_L^{h << fshift}, h < L >> fshift
+    const void* tw;       // w_NT^e, e < NT = max(n1, n2) (mixed-radix classes: NT = n1)
+    const void* tw2;      // roots of the column transforms: tw itself, or (mixed-radix
+                          // classes) w_n2^e, e < n2
+    const void* fa;       // w_L^{h << fshift}, h < ceil(L / 2^fshift)
     const void* fb;       // w_L^l, l < 1 << fshift
     int fshift;
     const void* stw;      // wave-transform stage tables, sizes 16..1024
@@ -76,7 +98,7 @@ struct ClassKernels {
 };
 
 // Registered by the per-precision kernel objects.
-const ClassKernels* class_kernels(int prec, int logL);
+const ClassKernels* class_kernels(int prec, int cls);
 
 constexpr int kMinLogL = 12;
 constexpr int kMaxLogL32 = 24;

@@ -46,11 +46,34 @@ int max_logL(int prec) {
     return cap;
 }
 
-bool class_geometry(int prec, int logL, ClassGeom* g) {
-    if (logL < 12 || logL > 24) return false;
+int ceil_log2(uint64_t L) {
+    int k = 0;
+    while ((1ull << k) < L) ++k;
+    return k;
+}
+
+bool class_geometry(int prec, int cls, ClassGeom* g) {
+    if (!class_id_valid(cls)) return false;
+    const uint64_t L = class_len(cls);
     g->prec = prec;
-    g->logL = logL;
+    g->cls = cls;
+    g->L = L;
     g->r = 16;
+    if (cls >= 32) {   // mixed-radix class L = P 2^k (FP32 and FP64 only)
+        if (prec != PREC_FP32 && prec != PREC_FP64) return false;
+        // power-of-two rows: those of the class 2^k below 2^20, else 8192;
+        // the columns carry the factor P (radix-P stage, 4P points per thread)
+        const int P = smooth_P(cls), k = smooth_k(cls);
+        ClassGeom base;
+        class_geometry(prec, k, &base);
+        g->n1 = L >= (1ull << 20) ? 8192 : base.n1;
+        g->n2 = (int)(L / (uint64_t)g->n1);
+        g->b1 = prec == PREC_FP64 ? 4 : 8;
+        g->b3 = prec == PREC_FP64 ? 8 : 16;
+        g->r = 4 * P;
+        return true;
+    }
+    const int logL = cls;
     if (prec == PREC_NTT) {
         const int n2log = std::min(11, logL / 2);
         g->n2 = 1 << n2log;
@@ -81,6 +104,31 @@ bool class_geometry(int prec, int logL, ClassGeom* g) {
     return true;
 }
 
+static uint64_t env_u64(const char* name) {
+    const char* e = getenv(name);
+    return e ? strtoull(e, nullptr, 10) : 0;
+}
+
+int class_ids(int prec, int* ids, int cap_logL) {
+    const uint64_t lo = 1ull << min_logL(prec), hi = 1ull << std::min(max_logL(prec), cap_logL);
+    const uint64_t only = env_u64("PA_ONLY_LEN");
+    const bool pow2 = env_u64("PA_POW2_ONLY") != 0;
+    int count = 0;
+    for (int id = kMinClassId; id <= kMaxClassId; ++id) {
+        ClassGeom g;
+        if (!class_geometry(prec, id, &g)) continue;
+        if (g.L < lo || g.L > hi || (only && g.L != only) || (pow2 && id >= 32)) continue;
+        ids[count++] = id;
+    }
+    std::sort(ids, ids + count, [](int a, int b) { return class_len(a) < class_len(b); });
+    return count;
+}
+
+uint64_t class_filter_key() {
+    return (uint64_t)min_logL(0) | ((uint64_t)max_logL(0) << 8) | ((env_u64("PA_POW2_ONLY") != 0 ? 1ull : 0ull) << 16) |
+           (env_u64("PA_ONLY_LEN") << 20);
+}
+
 void set_error_kappa(double kappa) { g_kappa = kappa; }
 double error_kappa() { return g_kappa; }
 
@@ -98,9 +146,9 @@ static double unit_roundoff(int prec) {
 // wave of rms u sqrt(sum_k 2 (D_k / 2)^4) / L; the sum converges like k^-4 and
 // 16 terms hold it (the rest is below 10^-4 of it).  The maximum over a tile
 // is about 2-4 times the rms.
-static double box_leak_rms(int prec, int logL, uint64_t Bi) {
-    const double L = std::ldexp(1.0, logL);
-    const uint64_t twoL = 2ull << logL;
+static double box_leak_rms(int prec, uint64_t Lc, uint64_t Bi) {
+    const double L = (double)Lc;
+    const uint64_t twoL = 2 * Lc;
     // sin(pi Bi k / L) and sin(pi k / L) for k = 1, 2, ... by rotation
     const double a = M_PI * (double)(Bi % twoL) / L, b = M_PI / L;
     const double sa = std::sin(a), ca = std::cos(a), sb = std::sin(b), cb = std::cos(b);
@@ -115,13 +163,13 @@ static double box_leak_rms(int prec, int logL, uint64_t Bi) {
     return unit_roundoff(prec) * std::sqrt(s4) / L;
 }
 
-double error_bound(int prec, int logL, uint64_t Bi) {
+double error_bound(int prec, uint64_t Lc, uint64_t Bi) {
     if (prec == PREC_NTT) return 0.0;
     // the noise term: the packed transform carries the seed's norm sqrt(L)
     // beside the chunk's sqrt(Bi), so even a one-bit chunk sees u sqrt(L log L)
-    const double L = std::ldexp(1.0, logL);
-    return 6.0 * g_kappa * unit_roundoff(prec) * std::sqrt((double)logL * ((double)Bi + L)) +
-           5.0 * box_leak_rms(prec, logL, Bi);
+    const double L = (double)Lc;
+    return 6.0 * g_kappa * unit_roundoff(prec) * std::sqrt(std::log2(L) * ((double)Bi + L)) +
+           5.0 * box_leak_rms(prec, Lc, Bi);
 }
 
 // Worst-case bound of Percival's form (Math. Comp. 72, 2003): an FFT
@@ -130,14 +178,17 @@ double error_bound(int prec, int logL, uint64_t Bi) {
 // (1+beta) for the twiddle (beta = 2u: table roots rounded once, four-step
 // roots an FP64 product rounded once) has max error at most
 // ||a|| ||b|| ((1+u)^3k (1+u sqrt5)^(3k+1) (1+beta)^3k - 1).  Read for this
-// pipeline: radix-4/8/16 stages count as their radix-2 levels, the spectrum
-// separation and the half-length Hermitian inverse add two levels (3k+2),
-// and the two sequences share one transform, so ||a|| ||b|| is replaced by
-// (||x|| + ||w||)^2 with ||x|| <= sqrt(Bi) (0/1 chunk) and ||w|| =
-// sqrt(Bi+Bo-1) (+-1 seed slice).  It holds for every input bit pattern.
-double rigorous_bound(int prec, int logL, uint64_t Bi, uint64_t Bo) {
+// pipeline: radix-4/8/16 stages count as their radix-2 levels, a radix-3/5/7
+// stage as ceil(log2 P) + 1 levels (k = ceil(log2 L) + 1 for a mixed-radix
+// length), the spectrum separation and the half-length Hermitian inverse add
+// two levels (3k+2), and the two sequences share one transform, so
+// ||a|| ||b|| is replaced by (||x|| + ||w||)^2 with ||x|| <= sqrt(Bi) (0/1
+// chunk) and ||w|| = sqrt(Bi+Bo-1) (+-1 seed slice).  It holds for every
+// input bit pattern.
+double rigorous_bound(int prec, uint64_t L, uint64_t Bi, uint64_t Bo) {
     if (prec == PREC_NTT || prec == PREC_DIRECT) return 0.0;
-    const double u = unit_roundoff(prec), lv = 3.0 * logL + 2.0, beta = 2.0 * u;
+    const int levels = ceil_log2(L) + ((L & (L - 1)) ? 1 : 0);
+    const double u = unit_roundoff(prec), lv = 3.0 * levels + 2.0, beta = 2.0 * u;
     const double g = lv * std::log1p(u) + (lv + 1) * std::log1p(u * std::sqrt(5.0)) + lv * std::log1p(beta);
     const double norms = std::sqrt((double)Bi) + std::sqrt((double)(Bi + Bo - 1));
     return norms * norms * std::expm1(g);
@@ -149,18 +200,27 @@ CostModel::CostModel() {
     // (256 CUs x 64 lanes x 2.4 GHz)
     direct_s = 1.0e-13;
     for (int p = 0; p < 3; ++p)
-        for (int k = 0; k < 32; ++k) {
-            const double L = std::ldexp(1.0, k);
+        for (int id = 0; id < 64; ++id) {
+            const uint64_t Lc = class_len(id);
+            if (Lc == 0) {
+                tile_s[p][id] = 1.0;
+                continue;
+            }
+            const double L = (double)Lc, lg = std::log2(L);
             // bytes moved by the three passes and a VALU estimate
             const double bytes = (p == 1 ? 48.0 : 24.0) * L;
-            const double instr = L * (5.0 * k + 40.0) * (p == 2 ? 3.0 : 1.0);
+            const double instr = L * (5.0 * lg + 40.0) * (p == 2 ? 3.0 : 1.0);
             const double t_mem = bytes / 5.0e12, t_alu = instr / 20.0e12;
-            tile_s[p][k] = std::max(t_mem, t_alu) + 1e-6;
+            // the long mixed-radix classes run workgroup-wide Stockham column
+            // passes, slower per point than the wave-level ones (measured on
+            // MI355X: about 1.8x in FP32 and 1.4x in FP64)
+            const double generic = (id >= 32 && Lc >= (1ull << 20)) ? (p == 1 ? 1.4 : 1.8) : 1.0;
+            tile_s[p][id] = generic * std::max(t_mem, t_alu) + 1e-6;
         }
 }
 
-double CostModel::tile(int prec, int logL) const { return tile_s[prec_index(prec)][logL]; }
-void CostModel::set(int prec, int logL, double s) { tile_s[prec_index(prec)][logL] = s; }
+double CostModel::tile(int prec, int cls) const { return tile_s[prec_index(prec)][cls]; }
+void CostModel::set(int prec, int cls, double s) { tile_s[prec_index(prec)][cls] = s; }
 
 double direct_cost(uint64_t n, uint64_t m, const CostModel& cm) {
     const double outs = (double)(ceil_div(m, 256) * 256), words = (double)(ceil_div(ceil_div(n, 32), 4) * 4);
@@ -173,14 +233,14 @@ bool choose_direct(uint32_t flags, uint64_t n, uint64_t m, const CostModel& cm, 
     return p == PA_PREC_AUTO && direct_cost(n, m, cm) < fft.cost;
 }
 
-bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& cm, TilePlan* out) {
+bool plan_at_class(uint64_t n, uint64_t m, int prec, int cls, const CostModel& cm, TilePlan* out) {
     ClassGeom g;
-    if (n == 0 || m == 0 || !class_geometry(prec, logL, &g)) return false;
-    const uint64_t L = 1ull << logL;
+    if (n == 0 || m == 0 || !class_geometry(prec, cls, &g)) return false;
+    const uint64_t L = g.L;
     // largest chunk the error model admits at this length
     uint64_t bi_cap = n;
     if (prec != PREC_NTT) {
-        const double per = 6.0 * g_kappa * unit_roundoff(prec) * std::sqrt((double)logL);
+        const double per = 6.0 * g_kappa * unit_roundoff(prec) * std::sqrt(std::log2((double)L));
         const double cap = std::floor((kPlanErrorLimit / per) * (kPlanErrorLimit / per) - (double)L);
         if (cap < (double)bi_cap) bi_cap = (uint64_t)std::max(0.0, cap);
     }
@@ -206,7 +266,8 @@ bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& 
         if (!found || tiles < best.tiles()) {
             found = true;
             best.prec = prec;
-            best.logL = logL;
+            best.cls = cls;
+            best.L = L;
             best.Bi = Bi;
             best.Bo = Bo;
             best.nchunks = nchunks;
@@ -215,10 +276,10 @@ bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& 
         if (nouts == 1 && nchunks == 1) break;
     }
     if (!found) return false;
-    best.bound = error_bound(prec, logL, best.Bi);
-    best.rigorous = rigorous_bound(prec, logL, best.Bi, best.Bo);
+    best.bound = error_bound(prec, L, best.Bi);
+    best.rigorous = rigorous_bound(prec, L, best.Bi, best.Bo);
     if (best.bound > kPlanErrorLimit) return false;   // not reached by FP32 up to 2^24
-    best.cost = (double)best.tiles() * cm.tile(prec, logL) + cm.launch_s;
+    best.cost = (double)best.tiles() * cm.tile(prec, cls) + cm.launch_s;
     *out = best;
     return true;
 }
@@ -226,17 +287,31 @@ bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& 
 bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan* out, int cap_logL) {
     if (n == 0 || m == 0) return false;
     const int prec = policy;
-    const int lo = min_logL(prec), hi = std::min(max_logL(prec), cap_logL);
+    int ids[kMaxClassId + 1];
+    const int nid = class_ids(prec, ids, cap_logL);
     if (prec == PREC_FP64 || prec == PREC_NTT) {
-        // one tile at the smallest class that holds the whole product
-        for (int k = lo; k <= hi; ++k)
-            if (n + m - 1 <= (1ull << k)) return plan_at_class(n, m, prec, k, cm, out);
+        // one tile: the cheapest class that holds the whole product (the
+        // shortest one unless a longer class runs faster kernels)
+        bool one = false;
+        TilePlan best1;
+        for (int q = 0; q < nid; ++q) {
+            TilePlan p;
+            if (n + m - 1 > class_len(ids[q]) || !plan_at_class(n, m, prec, ids[q], cm, &p)) continue;
+            if (!one || p.cost < best1.cost) {
+                best1 = p;
+                one = true;
+            }
+        }
+        if (one) {
+            *out = best1;
+            return true;
+        }
     }
     bool found = false;
     TilePlan best;
-    for (int k = lo; k <= hi; ++k) {
+    for (int q = 0; q < nid; ++q) {
         TilePlan p;
-        if (!plan_at_class(n, m, prec, k, cm, &p)) continue;
+        if (!plan_at_class(n, m, prec, ids[q], cm, &p)) continue;
         if (!found || p.cost < best.cost) {
             best = p;
             found = true;
@@ -249,14 +324,14 @@ bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan*
 bool plan_batch_groups(const std::vector<uint64_t>& ns, const std::vector<uint64_t>& ms, int policy,
                        const CostModel& cm, std::vector<BatchGroup>* groups, const std::vector<TilePlan>* own) {
     if (ns.empty() || ns.size() != ms.size() || (own && own->size() != ns.size())) return false;
-    // plans of job i at class k, computed once: memo[i * NK + k - 12], state 0
+    // plans of job i at class id k, computed once: memo[i * NK + k], state 0
     // unknown, 1 found, -1 none
-    constexpr int NK = 13;
+    constexpr int NK = kMaxClassId + 1;
     std::vector<TilePlan> memo(ns.size() * NK);
     std::vector<signed char> known(ns.size() * NK, 0);
     auto at_class = [&](size_t i, int k, TilePlan* p) {
-        const size_t x = i * NK + (size_t)(k - 12);
-        if (k < 12 || k >= 12 + NK) return false;
+        if (k < 0 || k >= NK) return false;
+        const size_t x = i * NK + (size_t)k;
         if (!known[x]) known[x] = plan_at_class(ns[i], ms[i], policy, k, cm, &memo[x]) ? 1 : -1;
         if (known[x] < 0) return false;
         *p = memo[x];
@@ -267,8 +342,8 @@ bool plan_batch_groups(const std::vector<uint64_t>& ns, const std::vector<uint64
         TilePlan p;
         if (own) p = (*own)[i];
         else if (!plan_job(ns[i], ms[i], policy, cm, &p)) return false;
-        BatchGroup& g = by_class[p.logL];
-        g.logL = p.logL;
+        BatchGroup& g = by_class[p.cls];
+        g.cls = p.cls;
         g.jobs.push_back(i);
         g.plans.push_back(p);
         g.cost += p.cost - cm.launch_s;
@@ -291,7 +366,7 @@ bool plan_batch_groups(const std::vector<uint64_t>& ns, const std::vector<uint64
                 bool ok = true;
                 for (size_t q = 0; q < gs[g].jobs.size() && ok; ++q) {
                     const size_t i = gs[g].jobs[q];
-                    ok = at_class(i, gs[h].logL, &moved[q]);
+                    ok = at_class(i, gs[h].cls, &moved[q]);
                     c += moved[q].cost - cm.launch_s;
                 }
                 if (!ok) continue;
@@ -312,18 +387,22 @@ bool plan_batch_groups(const std::vector<uint64_t>& ns, const std::vector<uint64
         }
         gs.erase(gs.begin() + (long)bg);
     }
-    std::sort(gs.begin(), gs.end(), [](const BatchGroup& a, const BatchGroup& b) { return a.logL < b.logL; });
+    std::sort(gs.begin(), gs.end(),
+              [](const BatchGroup& a, const BatchGroup& b) { return class_len(a.cls) < class_len(b.cls); });
     *groups = std::move(gs);
     return true;
 }
 
 bool plan_batch(const std::vector<uint64_t>& ns, const std::vector<uint64_t>& ms, int policy,
-                const CostModel& cm, int* logL_out, std::vector<TilePlan>* plans) {
+                const CostModel& cm, int* cls_out, std::vector<TilePlan>* plans) {
     if (ns.empty() || ns.size() != ms.size()) return false;
     bool found = false;
     double best_cost = 0;
     std::vector<TilePlan> tmp(ns.size());
-    for (int k = min_logL(policy); k <= max_logL(policy); ++k) {
+    int ids[kMaxClassId + 1];
+    const int nid = class_ids(policy, ids);
+    for (int q = 0; q < nid; ++q) {
+        const int k = ids[q];
         double cost = cm.launch_s;
         bool ok = true;
         for (size_t i = 0; i < ns.size() && ok; ++i) {
@@ -334,7 +413,7 @@ bool plan_batch(const std::vector<uint64_t>& ns, const std::vector<uint64_t>& ms
         if (!found || cost < best_cost) {
             found = true;
             best_cost = cost;
-            *logL_out = k;
+            *cls_out = k;
             *plans = tmp;
         }
     }

@@ -5,32 +5,47 @@
 #include <cstdint>
 #include <vector>
 
+#include "pa_internal.hpp"
+
 namespace pa {
 
 enum Prec { PREC_FP32 = 32, PREC_FP64 = 64, PREC_NTT = 1, PREC_DIRECT = 2 };
 
 struct ClassGeom {
-    int prec, logL, n1, n2, b1, b3, r;
+    int prec, cls;        // precision, class id (pa_internal.hpp)
+    uint64_t L;           // FFT length n1 * n2
+    int n1, n2, b1, b3, r;
 };
 
-// Geometry of the length class 2^logL in the given precision; false if none.
-bool class_geometry(int prec, int logL, ClassGeom* g);
+// Geometry of class `cls` in the given precision; false if none.
+bool class_geometry(int prec, int cls, ClassGeom* g);
+// ceil(log2 L)
+int ceil_log2(uint64_t L);
 int min_logL(int prec);
 int max_logL(int prec);
+// The class ids a plan of precision `prec` may use, in increasing FFT length:
+// 2^min_logL <= L <= 2^min(max_logL, cap_logL).  Environment (tests and
+// measurements): PA_MIN_LOG2_LEN / PA_MAX_LOG2_LEN bound L; PA_ONLY_LEN=<L>
+// keeps the class of that length only; PA_POW2_ONLY=1 drops the mixed-radix
+// classes.  Writes at most kMaxClassId + 1 ids; returns the count.
+int class_ids(int prec, int* ids, int cap_logL = 24);
+// A key of the environment settings above (plan caches depend on them).
+uint64_t class_filter_key();
 
-// Cost per tile (seconds) of a class, by prec and logL.  Filled from tuning
-// data when present, else from the built-in model.
+// Cost per tile (seconds) of a class, by prec and class id.  Filled from
+// tuning data when present, else from the built-in model.
 struct CostModel {
-    double tile_s[3][32];   // [0] FP32, [1] FP64, [2] NTT; index logL
+    double tile_s[3][64];   // [0] FP32, [1] FP64, [2] NTT; index class id
     double launch_s;        // fixed cost of one pipeline launch
     double direct_s;        // direct GF(2) path: seconds per output per 32-bit key word
     CostModel();
-    double tile(int prec, int logL) const;
-    void set(int prec, int logL, double s);
+    double tile(int prec, int cls) const;
+    void set(int prec, int cls, double s);
 };
 
 struct TilePlan {
-    int prec = 0, logL = 0;
+    int prec = 0, cls = 0;
+    uint64_t L = 0;        // FFT length of the class
     uint64_t Bi = 0, Bo = 0, nchunks = 0, nouts = 0;
     double bound = 0, cost = 0;
     double rigorous = 0;   // worst-case rounding bound of a tile (any input bits)
@@ -39,16 +54,16 @@ struct TilePlan {
 
 // Error model of one floating-point tile, a predicted maximum of the output
 // error for an FFT convolution of a +-1 sequence with a 0/1 chunk of Bi bits at
-// length 2^logL: 6 sigma of the random rounding noise, sigma = kappa u
-// sqrt(logL (Bi + L)), plus 5 times the rms of the low-frequency error that the
-// chunk's zero padding causes (about 0.036 u L once Bi > L/3; the larger term
-// from 2^22 on in FP32).
-double error_bound(int prec, int logL, uint64_t Bi);
+// length L: 6 sigma of the random rounding noise, sigma = kappa u
+// sqrt(log2 L (Bi + L)), plus 5 times the rms of the low-frequency error that
+// the chunk's zero padding causes (about 0.036 u L once Bi > L/3; the larger
+// term from 2^22 on in FP32).
+double error_bound(int prec, uint64_t L, uint64_t Bi);
 // Worst-case (a-priori) bound of a tile's max error for any input bits:
 // (||x|| + ||w||)^2 times the relative error growth of the forward FFT,
 // product and inverse FFT, with ||x|| <= sqrt(Bi), ||w|| = sqrt(Bi+Bo-1).  A
 // tile whose bound is below 0.5 rounds to the exact integers.
-double rigorous_bound(int prec, int logL, uint64_t Bi, uint64_t Bo);
+double rigorous_bound(int prec, uint64_t L, uint64_t Bi, uint64_t Bo);
 constexpr double kRigorousLimit = 0.5;
 void set_error_kappa(double kappa);
 double error_kappa();
@@ -66,25 +81,26 @@ double direct_cost(uint64_t n, uint64_t m, const CostModel& cm);
 bool choose_direct(uint32_t flags, uint64_t n, uint64_t m, const CostModel& cm, const TilePlan& fft);
 
 // Best (Bi, Bo) for job (n, m) at a fixed class; false if impossible.
-bool plan_at_class(uint64_t n, uint64_t m, int prec, int logL, const CostModel& cm, TilePlan* out);
+bool plan_at_class(uint64_t n, uint64_t m, int prec, int cls, const CostModel& cm, TilePlan* out);
 
 // Best plan over classes for one job.  policy: PREC_FP32 (segmented, bound
-// limited), PREC_FP64 (smallest single tile if one fits, else the cheapest
-// plan over the classes), PREC_NTT.  Classes above 2^cap_logL are not used.
+// limited), PREC_FP64 and PREC_NTT (the cheapest single tile if one fits, else
+// the cheapest plan over the classes).  Classes longer than 2^cap_logL are not
+// used.
 bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan* out, int cap_logL = 24);
 
 // Jobs of a batch that share one FFT length class (one pipeline launch).
 struct BatchGroup {
-    int logL = 0;
+    int cls = 0;
     std::vector<size_t> jobs;      // indices into the batch
-    std::vector<TilePlan> plans;   // plan of each job in `jobs`, at logL
+    std::vector<TilePlan> plans;   // plan of each job in `jobs`, at class cls
     double cost = 0;               // launch plus tiles
 };
 
 // Batch plan with one launch per length class: every job starts in its own
 // cheapest class, then a group is folded into another group's class while that
 // lowers the summed cost (tiles plus one launch per group).  Groups come out
-// in increasing logL.  `own` (optional): each job's own best plan, already
+// in increasing FFT length.  `own` (optional): each job's own best plan, already
 // known to the caller.
 bool plan_batch_groups(const std::vector<uint64_t>& ns, const std::vector<uint64_t>& ms, int policy,
                        const CostModel& cm, std::vector<BatchGroup>* groups,
@@ -92,6 +108,6 @@ bool plan_batch_groups(const std::vector<uint64_t>& ns, const std::vector<uint64
 
 // One class for a whole batch: minimises the summed cost of every job's tiles.
 bool plan_batch(const std::vector<uint64_t>& ns, const std::vector<uint64_t>& ms, int policy,
-                const CostModel& cm, int* logL, std::vector<TilePlan>* plans);
+                const CostModel& cm, int* cls, std::vector<TilePlan>* plans);
 
 }  // namespace pa

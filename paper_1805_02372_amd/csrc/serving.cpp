@@ -63,8 +63,8 @@ static uint64_t request_bytes(Ctx* c, uint64_t n, uint64_t m, uint64_t* min_byte
         *cls = 0;
         return ~0ull;
     }
-    *min_bytes = (uint64_t)8 << p.logL;
-    *cls = p.logL;
+    *min_bytes = 8 * p.L;
+    *cls = p.cls;
     return p.tiles() * *min_bytes;
 }
 
@@ -203,7 +203,7 @@ void Ctx::serve_loop() {
                 }
                 continue;
             }
-            const int logL = cls0;
+            const int cls = cls0;
             CostModel cm;
             {
                 std::lock_guard<std::mutex> pl(plan_mu);
@@ -212,7 +212,7 @@ void Ctx::serve_loop() {
             std::vector<TilePlan> plans(batch.size());
             pa_status s = PA_OK;
             for (size_t k = 0; k < batch.size() && s == PA_OK; ++k)
-                if (!plan_at_class(ns[k], ms[k], PREC_FP32, logL, cm, &plans[k])) s = PA_EINVAL;
+                if (!plan_at_class(ns[k], ms[k], PREC_FP32, cls, cm, &plans[k])) s = PA_EINVAL;
             std::vector<JobDesc> jobs(batch.size());
             if (s == PA_OK) {
                 for (size_t k = 0; k < batch.size(); ++k)
@@ -220,7 +220,7 @@ void Ctx::serve_loop() {
                              batch[k]->n, batch[k]->m, plans[k]);
                 lane_stats[i] = pa_stats{};
                 for (const TilePlan& tp : plans) fill_plan_stats(&lane_stats[i], tp);
-                s = lanes[i].launch(this, PREC_FP32, logL, jobs, false, true, &lane_stats[i]);
+                s = lanes[i].launch(this, PREC_FP32, cls, jobs, false, true, &lane_stats[i]);
             }
             lk.lock();
             if (s != PA_OK) {

@@ -40,16 +40,23 @@ static void roots(std::vector<T>& out, uint64_t count, uint64_t N, uint64_t mult
     }
 }
 
+static int log2_ceil(uint64_t L) {
+    int k = 0;
+    while ((1ull << k) < L) ++k;
+    return k;
+}
+
 template <typename T>
-void build_tables(int logL, int n1, int n2, TableHost<T>* th) {
-    const uint64_t L = 1ull << logL;
-    const uint64_t NT = (uint64_t)(n1 > n2 ? n1 : n2);
-    th->fshift = (logL + 1) / 2;
+void build_tables(uint64_t L, int n1, int n2, bool smooth, TableHost<T>* th) {
+    const uint64_t NT = smooth ? (uint64_t)n1 : (uint64_t)(n1 > n2 ? n1 : n2);
+    th->fshift = (log2_ceil(L) + 1) / 2;
+    const uint64_t nfa = (L + (1ull << th->fshift) - 1) >> th->fshift;
     roots(th->tw, NT, NT, 1);
-    roots(th->fa, L >> th->fshift, L, 1ull << th->fshift);
+    if (smooth) roots(th->tw2, (uint64_t)n2, (uint64_t)n2, 1);
+    roots(th->fa, nfa, L, 1ull << th->fshift);
     roots(th->fb, 1ull << th->fshift, L, 1);
     if (sizeof(T) < sizeof(double)) {
-        roots(th->fa64, L >> th->fshift, L, 1ull << th->fshift);
+        roots(th->fa64, nfa, L, 1ull << th->fshift);
         roots(th->fb64, 1ull << th->fshift, L, 1);
     }
     // stage tables: size M, stage span Ns (> 1), radix 16: entry [k][r] = w_{16 Ns}^{k r}
@@ -69,7 +76,7 @@ void build_tables(int logL, int n1, int n2, TableHost<T>* th) {
     }
 }
 
-template void build_tables<float>(int, int, int, TableHost<float>*);
+template void build_tables<float>(uint64_t, int, int, bool, TableHost<float>*);
 
 namespace {
 constexpr uint64_t kP = 2013265921ull;  // 15 * 2^27 + 1
@@ -87,10 +94,9 @@ uint64_t powmod(uint64_t a, uint64_t e) {
 uint32_t to_mont(uint64_t a) { return (uint32_t)(((a % kP) << 32) % kP); }
 }  // namespace
 
-void build_ntt_tables(int logL, int n1, int n2, TableHost<uint32_t>* th) {
-    const uint64_t L = 1ull << logL;
+void build_ntt_tables(uint64_t L, int n1, int n2, TableHost<uint32_t>* th) {
     const uint64_t NT = (uint64_t)(n1 > n2 ? n1 : n2);
-    th->fshift = (logL + 1) / 2;
+    th->fshift = (log2_ceil(L) + 1) / 2;
     const uint64_t wNT = powmod(31, (kP - 1) / NT), wL = powmod(31, (kP - 1) / L);
     th->tw.resize(NT);
     uint64_t a = 1;
@@ -105,6 +111,6 @@ void build_ntt_tables(int logL, int n1, int n2, TableHost<uint32_t>* th) {
     for (uint64_t l = 0; l < nfb; ++l, a = mulmod(a, wL)) th->fb[l] = to_mont(a);
     th->stw = {(uint32_t)powmod(L, kP - 2), to_mont(1)};
 }
-template void build_tables<double>(int, int, int, TableHost<double>*);
+template void build_tables<double>(uint64_t, int, int, bool, TableHost<double>*);
 
 }  // namespace pa

@@ -32,7 +32,13 @@ static pa_status save_json(const CostModel& cm, const std::vector<int>& precs, c
     fprintf(f, "{\"launch\": %.9g, \"direct\": %.9g", cm.launch_s, cm.direct_s);
     for (size_t i = 0; i < precs.size(); ++i) {
         fprintf(f, ", \"%s\": {", prec_key(precs[i]));
-        for (int k = 12; k <= 24; ++k) fprintf(f, "%s\"%d\": %.9g", k > 12 ? ", " : "", k, cm.tile(precs[i], k));
+        bool first = true;
+        for (int k = kMinClassId; k <= kMaxClassId; ++k) {
+            ClassGeom g;
+            if (!class_geometry(precs[i], k, &g)) continue;
+            fprintf(f, "%s\"%llu\": %.9g", first ? "" : ", ", (unsigned long long)g.L, cm.tile(precs[i], k));
+            first = false;
+        }
         fprintf(f, "}");
     }
     fprintf(f, "}\n");
@@ -69,8 +75,10 @@ static pa_status load_json(CostModel& cm, const char* path) {
         const size_t open = text.find('{', at), close = text.find('}', at);
         if (open == std::string::npos || close == std::string::npos || close < open) return PA_EINVAL;
         const std::string body = text.substr(open + 1, close - open - 1);
-        for (int k = 12; k <= 24; ++k) {
-            const std::string key = "\"" + std::to_string(k) + "\":";
+        for (int k = kMinClassId; k <= kMaxClassId; ++k) {
+            ClassGeom g;
+            if (!class_geometry(prec, k, &g)) continue;
+            const std::string key = "\"" + std::to_string(g.L) + "\":";
             size_t p = body.find(key);
             if (p == std::string::npos) continue;
             const double v = strtod(body.c_str() + p + key.size(), nullptr);
@@ -83,10 +91,10 @@ static pa_status load_json(CostModel& cm, const char* path) {
     return loaded ? PA_OK : PA_EINVAL;
 }
 
-// Kernel time (s) of one launch of `count` identical one-tile jobs of class k.
+// Kernel time (s) of one launch of `count` identical one-tile jobs of class id k.
 static pa_status time_launch(Ctx* c, int prec, int k, const TilePlan& p, int count, uint64_t* dseed,
                              uint64_t* dkey, uint64_t* douts, uint64_t out_words, int reps, double* best) {
-    const uint64_t L = 1ull << k;
+    const uint64_t L = class_len(k);
     *best = 1e30;
     for (int r = 0; r <= reps; ++r) {  // the first run warms tables and workspace
         std::vector<JobDesc> jobs(count);
@@ -140,9 +148,12 @@ pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path) {
         cm = c->cost;
     }
     std::vector<double> fixed;
-    for (int prec : precs)
-        for (int k = 12; k <= 24; ++k) {
-            const uint64_t L = 1ull << k;
+    for (int prec : precs) {
+        int ids[kMaxClassId + 1];
+        const int nid = class_ids(prec, ids);
+        for (int q = 0; q < nid; ++q) {
+            const int k = ids[q];
+            const uint64_t L = class_len(k);
             TilePlan p;
             if (!plan_at_class(L / 2, L / 2 + 1, prec, k, cm, &p) || p.tiles() != 1) continue;
             double t1 = 0, t4 = 0;
@@ -157,6 +168,7 @@ pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path) {
             cm.set(prec, k, marginal);
             fixed.push_back(std::max(t1 - marginal, 0.0));
         }
+    }
     // direct path: the slope between two output lengths at n = 2^22 is the
     // cost per output and 32-bit key word
     const uint32_t pbits = flags & PA_PREC_MASK;

@@ -58,7 +58,7 @@ class pa_stats(ctypes.Structure):
                 ("max_residual", ctypes.c_double), ("max_abs", ctypes.c_double), ("bound", ctypes.c_double),
                 ("ms_pass", ctypes.c_double * 4), ("model_bytes", ctypes.c_uint64), ("launches", ctypes.c_uint64),
                 ("direct_jobs", ctypes.c_uint64), ("rigorous_bound", ctypes.c_double), ("certified", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("live_requests", ctypes.c_uint64)]
+                ("fft_len", ctypes.c_uint32), ("live_requests", ctypes.c_uint64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -71,7 +71,7 @@ class pa_plan(ctypes.Structure):
                 ("n2", ctypes.c_uint32), ("chunk_bits", ctypes.c_uint64), ("window_bits", ctypes.c_uint64),
                 ("chunks", ctypes.c_uint64), ("windows", ctypes.c_uint64), ("bound", ctypes.c_double),
                 ("cost", ctypes.c_double), ("direct_cost", ctypes.c_double), ("direct", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("rigorous_bound", ctypes.c_double)]
+                ("fft_len", ctypes.c_uint32), ("rigorous_bound", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -187,7 +187,7 @@ def test_timing_stats(pa, ctx):
     assert pa.pa_hash(ctx, s, n, m, k, o, pa.PA_PREC_AUTO | pa.PA_TIMING) == pa.PA_OK
     st = pa.pa_last_stats(ctx)
     assert all(x > 0 for x in st["ms_pass"][:3]), st
-    assert st["model_bytes"] == st["tiles"] * 24 * (1 << st["log2_len"])
+    assert st["model_bytes"] == st["tiles"] * 24 * st["fft_len"]
 
 
 # ------------------------------------------------------------------ serving
@@ -329,7 +329,10 @@ def test_tune_writes_and_loads(pa, ctx, tmp_path):
     assert pa.pa_tune(ctx, pa.PA_PREC_FP32_SEG, 1, path) == pa.PA_OK
     data = json.load(open(path))
     assert data["direct"] > 0   # the built-in direct-path cost (not timed for FP32_SEG)
-    costs = [data["fp32"][str(k)] for k in range(12, 25)]
+    # keyed by FFT length: every class, power-of-two and mixed-radix
+    lens = sorted(int(k) for k in data["fp32"])
+    assert {1 << k for k in range(12, 25)} <= set(lens) and {3 << 22, 5 << 21, 7 << 21} <= set(lens)
+    costs = [data["fp32"][str(L)] for L in lens]
     assert all(c > 0 for c in costs)
     assert 0 <= data["launch"] < 1e-2   # per-launch cost in seconds
     assert costs[-1] > costs[0]          # longer transforms cost more

@@ -63,6 +63,11 @@ def tiles_of(n, m, plan):
     return out
 
 
+# FFT lengths of the classes: 2^12 .. 2^24, and 3, 5, 7 times 2^k between
+# 2^14 and 2^24 (FP32 and FP64)
+CLASS_LENS = {1 << k for k in range(12, 25)} | {p << k for p in (3, 5, 7) for k in range(11, 23)
+                                                if (1 << 14) < (p << k) < (1 << 24)}
+
 SHAPES = [(1, 1), (5, 3), (131072, 16384), (1_000_000, 200_000), (12_345_679, 1_234_567),
           (100_000_000, 50_000_000), (3, 40_000_000), (40_000_000, 3), (16_777_216, 1), (2**24, 2**24)]
 
@@ -72,8 +77,9 @@ SHAPES = [(1, 1), (5, 3), (131072, 16384), (1_000_000, 200_000), (12_345_679, 1_
 def test_plan_covers_every_pair_once(pa, n, m, prec):
     flags = {"auto": pa.PA_PREC_AUTO, "fp32": pa.PA_PREC_FP32_SEG, "fp64": pa.PA_PREC_FP64}[prec]
     p = pa.pa_plan_query(n, m, flags)
-    L = 1 << p["log2_len"]
-    assert p["n1"] * p["n2"] == L
+    L = p["fft_len"]
+    assert p["n1"] * p["n2"] == L and 1 << p["log2_len"] >= L > 1 << (p["log2_len"] - 1)
+    assert L in CLASS_LENS
     Bi, Bo = p["chunk_bits"], p["window_bits"]
     assert p["chunks"] == -(-n // Bi) and p["windows"] == -(-m // Bo)
     assert Bi + Bo - 1 <= L                       # no wrap into the kept window
@@ -109,7 +115,10 @@ def test_plan_invariants_random_shapes(pa):
                f=st.sampled_from([pa.PA_PREC_AUTO, pa.PA_PREC_FP64, pa.PA_PREC_NTT]))
     def check(n, m, f):
         p = pa.pa_plan_query(n, m, f)
-        L = 1 << p["log2_len"]
+        L = p["fft_len"]
+        assert p["n1"] * p["n2"] == L and L in CLASS_LENS
+        if f == pa.PA_PREC_NTT:
+            assert L & (L - 1) == 0               # the NTT has power-of-two classes only
         Bi, Bo, C, W = p["chunk_bits"], p["window_bits"], p["chunks"], p["windows"]
         assert Bi + Bo - 1 <= L
         assert C == -(-n // Bi) and W == -(-m // Bo) and (C - 1) * Bi < n and (W - 1) * Bo < m
@@ -266,3 +275,40 @@ def test_rigorous_bound_fp32(pa):
     c3 = pa.pa_plan_query(12_345_679, 1_234_567, pa.PA_PREC_FP32_SEG)
     assert c3["rigorous_bound"] > 0.5, c3
     assert c3["rigorous_bound"] > 100 * c3["bound"], c3
+
+
+def test_mixed_radix_classes_shorten_the_plain_fp64_tile(pa, monkeypatch):
+    """Section 3, step 1 pads the product to an arbitrary length.  The plain
+    FP64 path runs one tile; the shortest class that holds n + m - 1 is
+    within 1.25x of it with the classes 3, 5 and 7 times 2^k, and the path
+    takes the cheapest single tile by the cost model (never longer than the
+    next power of two)."""
+    import math
+    for n, m, want in [(131_072, 16_384, 163_840),          # c1: 5 * 2^15 (2^18 without)
+                       (1_000_000, 200_000, 1_310_720),     # c2: 5 * 2^18 (2^21 without)
+                       (12_345_679, 1_234_567, 14_680_064)]:  # c3: 7 * 2^21 (2^24 without)
+        assert want == min(x for x in CLASS_LENS if x >= n + m - 1)
+        monkeypatch.setenv("PA_ONLY_LEN", str(want))
+        p = pa.pa_plan_query(n, m, pa.PA_PREC_FP64)
+        assert p["fft_len"] == want and p["chunks"] == p["windows"] == 1, p
+        assert p["log2_len"] == math.ceil(math.log2(want))
+        monkeypatch.delenv("PA_ONLY_LEN")
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        n, m = int(rng.integers(1, 1 << 23)), int(rng.integers(1, 1 << 23))
+        if n + m - 1 > 1 << 24 or n + m - 1 <= 1 << 14:
+            continue
+        p = pa.pa_plan_query(n, m, pa.PA_PREC_FP64)
+        L = p["fft_len"]
+        assert p["chunks"] == p["windows"] == 1 and n + m - 1 <= L <= 1 << math.ceil(math.log2(n + m - 1)), (n, m, L)
+
+
+def test_class_filters(pa, monkeypatch):
+    """PA_POW2_ONLY keeps the power-of-two classes; PA_ONLY_LEN pins one class."""
+    monkeypatch.setenv("PA_POW2_ONLY", "1")
+    assert pa.pa_plan_query(12_345_679, 1_234_567, pa.PA_PREC_FP64)["fft_len"] == 1 << 24
+    monkeypatch.delenv("PA_POW2_ONLY")
+    monkeypatch.setenv("PA_ONLY_LEN", str(3 << 16))
+    for f in (pa.PA_PREC_FP32_SEG, pa.PA_PREC_FP64):
+        p = pa.pa_plan_query(1_000_000, 300_000, f)
+        assert p["fft_len"] == 3 << 16 and p["chunks"] * p["windows"] > 1, p

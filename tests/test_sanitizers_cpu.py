@@ -29,14 +29,19 @@ int main() {
                 TilePlan tp;
                 if (plan_job(n, m, p, cm, &tp)) {
                     ++plans;
-                    if (tp.Bi + tp.Bo - 1 > (1ull << tp.logL)) return 2;
+                    if (tp.Bi + tp.Bo - 1 > tp.L || tp.L != class_len(tp.cls)) return 2;
                     (void)choose_direct(PA_PREC_AUTO, n, m, cm, tp);
                 }
                 (void)direct_cost(n, m, cm);
             }
-    for (int k = 12; k <= 24; ++k)
-        for (uint64_t bi : {1ull, 1000ull, 1ull << (k - 1), (1ull << k) - 1})
-            (void)error_bound(PREC_FP32, k, bi);
+    for (int id = kMinClassId; id <= kMaxClassId; ++id) {
+        const uint64_t L = class_len(id);
+        if (L == 0) continue;
+        for (uint64_t bi : {(uint64_t)1, (uint64_t)1000, L / 2, L - 1}) {
+            (void)error_bound(PREC_FP32, L, bi);
+            (void)rigorous_bound(PREC_FP64, L, bi, L - bi + 1);
+        }
+    }
     std::vector<uint64_t> ns, ms;
     for (int i = 0; i < 64; ++i) {
         ns.push_back(100000 + 154321ull * i);
