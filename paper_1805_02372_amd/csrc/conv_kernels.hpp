@@ -92,6 +92,33 @@ __device__ __forceinline__ void put_bits(const TileGeo& g, uint64_t off, uint32_
     }
 }
 
+// Bits [pos, pos + cnt) of a bit string (cnt <= 64), LSB first.
+__device__ __forceinline__ uint64_t extract_bits(const uint64_t* __restrict__ a, uint64_t pos, uint32_t cnt) {
+    if (cnt == 0) return 0;
+    const uint64_t w = pos >> 6;
+    const uint32_t s = (uint32_t)(pos & 63);
+    uint64_t v = a[w] >> s;
+    if (s + cnt > 64) v |= a[w + 1] << (64 - s);
+    return cnt >= 64 ? v : (v & ((1ull << cnt) - 1));
+}
+
+// Key bits of the placed chunk for C consecutive positions t = s0 .. s0+C-1:
+// position t holds key bit j0 + ((t + bi - 1) mod L) when that index is < bi.
+template <int C>
+__device__ __forceinline__ uint64_t placed_key_bits(const uint64_t* __restrict__ key, uint64_t j0, uint32_t bi,
+                                                    uint32_t L, uint32_t s0) {
+    uint32_t u0 = s0 + bi - 1;
+    if (u0 >= L) u0 -= L;
+    auto part = [&](uint32_t ustart, uint32_t fstart, uint32_t count) -> uint64_t {
+        if (ustart >= bi || count == 0) return 0;
+        const uint32_t nv = (bi - ustart) < count ? (bi - ustart) : count;
+        return extract_bits(key, j0 + ustart, nv) << fstart;
+    };
+    if (u0 + C <= L) return part(u0, 0, C);
+    const uint32_t fs = L - u0;  // positions at and after fs wrap to the start
+    return part(u0, 0, fs) | part(0, fs, C - fs);
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> four_step_root(const cx<T>* __restrict__ fa, const cx<T>* __restrict__ fb,
                                                 int fshift, uint32_t e) {
@@ -121,28 +148,34 @@ k_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part,
     if (tid == 0) wsum = 0;
     clear_window(g, cb, NCB, tid, B * (N2 / R));
 
+    // Stage this workgroup's key and seed bits in LDS: per row t2 the B-bit
+    // fields at positions cb B + N1 t2 .. + B - 1 (key bits low, seed bits
+    // high), read as funnel-shifted words instead of one load per point.  The
+    // FFT's first barrier precedes its first LDS write.
+    static_assert(B <= 8 && 2 * N2 <= lds_slots<N2, B>() * (int)sizeof(cx<T>), "bit fields");
+    constexpr int NTH = B * (N2 / R);
+    uint16_t* fld = reinterpret_cast<uint16_t*>(lds);
     const uint32_t bi = (uint32_t)g.bi, win = (uint32_t)(g.bi + g.bo - 1);
     uint32_t pc = 0;
+    for (int r = tid; r < N2; r += NTH) {
+        const uint32_t s0 = cb * B + (uint32_t)N1 * (uint32_t)r;
+        const uint32_t kbits = (uint32_t)placed_key_bits<B>(jd.key, g.j0, bi, L, s0);
+        const uint32_t nv = s0 < win ? ((win - s0) < (uint32_t)B ? (win - s0) : (uint32_t)B) : 0u;
+        const uint32_t sbits = (uint32_t)extract_bits(jd.seed, g.sigma + s0, nv);
+        fld[r] = (uint16_t)(kbits | (sbits << 8));
+        pc += (uint32_t)__popc(kbits);
+    }
+    __syncthreads();
     cx<T> v[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        const uint32_t tt = t1 + (uint32_t)N1 * (uint32_t)(j + i * NR);
-        uint32_t u = tt + bi - 1;                  // key chunk at offset -(bi-1)
-        if (u >= L) u -= L;
-        uint32_t xb = 0;
-        if (u < bi) {
-            const uint64_t kb = g.j0 + u;
-            xb = (uint32_t)(jd.key[kb >> 6] >> (kb & 63)) & 1u;
-        }
-        T wv = T(0);
-        if (tt < win) {
-            const uint64_t sb = g.sigma + tt;
-            wv = ((jd.seed[sb >> 6] >> (sb & 63)) & 1u) ? T(1) : T(-1);
-        }
-        v[i] = cx<T>{(T)xb, wv};
-        pc += xb;
+        const uint32_t t2 = (uint32_t)(j + i * NR);
+        const uint32_t tt = t1 + (uint32_t)N1 * t2;
+        const uint32_t w = fld[t2];
+        const T xb = ((w >> f) & 1u) ? T(1) : T(0);
+        const T sv = ((w >> (8 + f)) & 1u) ? T(1) : T(-1);
+        v[i] = cx<T>{xb, tt < win ? sv : T(0)};
     }
-    __syncthreads();
     atomicAdd(&wsum, pc);
 
     fft<T, -1, N2, R, B, NT>(v, lds, j, f, tw);
@@ -303,18 +336,29 @@ k_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta, 
     const int64_t weight = (int64_t)meta[t].popcnt;
 
     // Hermitian column H[k] = V[k][t1] (k < n2/2), H[n2/2] in the imaginary
-    // part of row 0 (SPLIT: the real part of row n2/2).  U[k] = E[k] + i O[k] with E = H[k] + conj H[n2/2-k],
-    // O = (H[k] - conj H[n2/2-k]) w_n2^{-k}.
+    // part of row 0 (SPLIT: the real part of row n2/2).  The block of B
+    // columns is read once as B-element row segments into LDS, where each
+    // thread pairs k with n2/2 - k.  U[k] = E[k] + i O[k] with
+    // E = H[k] + conj H[n2/2-k], O = (H[k] - conj H[n2/2-k]) w_n2^{-k}.
+    constexpr int NTH = B * (N2h / R);
+    __shared__ T hrow[B];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int x = tid + q * NTH, k = x / B, c = x % B;
+        lds[lds_slot<B>(k, c)] = V[(size_t)k * N1 + cb * B + c];
+    }
+    if (tid < B) hrow[tid] = SPLIT ? V[(size_t)N2h * N1 + cb * B + tid].re : V[cb * B + tid].im;
+    __syncthreads();
     cx<T> v[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const int k = j + i * NR;
-        const cx<T> h = V[(size_t)k * N1 + t1];
+        const cx<T> h = lds[lds_slot<B>(k, f)];
         if (k == 0) {
-            const T hh = SPLIT ? V[(size_t)N2h * N1 + t1].re : h.im;   // H[n2/2]
+            const T hh = hrow[f];   // H[n2/2]
             v[i] = cx<T>{h.re + hh, h.re - hh};
         } else {
-            const cx<T> hm = conj(V[(size_t)(N2h - k) * N1 + t1]);
+            const cx<T> hm = conj(lds[lds_slot<B>(N2h - k, f)]);
             const cx<T> e = h + hm;
             const cx<T> o = cmulc(h - hm, tw[k * (NT / N2)]);
             v[i] = cx<T>{e.re - o.im, e.im + o.re};

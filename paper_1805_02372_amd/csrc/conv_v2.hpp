@@ -57,32 +57,6 @@ template <typename T, int N2> struct P3Geom {
 // Transposition tile: row k2 of C elements, columns XOR-swizzled by the row.
 template <int C> __device__ __forceinline__ int tslot(int k, int f) { return k * C + (f ^ (k & (C - 1))); }
 
-__device__ __forceinline__ uint64_t extract_bits(const uint64_t* __restrict__ a, uint64_t pos, uint32_t cnt) {
-    if (cnt == 0) return 0;
-    const uint64_t w = pos >> 6;
-    const uint32_t s = (uint32_t)(pos & 63);
-    uint64_t v = a[w] >> s;
-    if (s + cnt > 64) v |= a[w + 1] << (64 - s);
-    return cnt >= 64 ? v : (v & ((1ull << cnt) - 1));
-}
-
-// Key bits of the placed chunk for C consecutive positions t = s0 .. s0+C-1:
-// position t holds key bit j0 + ((t + bi - 1) mod L) when that index is < bi.
-template <int C>
-__device__ __forceinline__ uint64_t placed_key_bits(const uint64_t* __restrict__ key, uint64_t j0, uint32_t bi,
-                                                    uint32_t L, uint32_t s0) {
-    uint32_t u0 = s0 + bi - 1;
-    if (u0 >= L) u0 -= L;
-    auto part = [&](uint32_t ustart, uint32_t fstart, uint32_t count) -> uint64_t {
-        if (ustart >= bi || count == 0) return 0;
-        const uint32_t nv = (bi - ustart) < count ? (bi - ustart) : count;
-        return extract_bits(key, j0 + ustart, nv) << fstart;
-    };
-    if (u0 + C <= L) return part(u0, 0, C);
-    const uint32_t fs = L - u0;  // positions at and after fs wrap to the start
-    return part(u0, 0, fs) | part(0, fs, C - fs);
-}
-
 // ------------------------------------------------------------------ FP64 roots
 // Four-step twiddles are formed as FP64 products of two-level tables and
 // rounded once to the working precision: w_L^e = fa64[e >> fshift] fb64[e & mask].

@@ -101,6 +101,128 @@ void HostBuf::release() {
     bytes = 0;
 }
 
+// ------------------------------------------------------------ host staging
+
+bool CopyPool::take_part(int* p) {
+    if (taken >= nparts) return false;
+    *p = taken++;
+    return true;
+}
+
+void CopyPool::work() {
+    std::unique_lock<std::mutex> lk(mu);
+    uint64_t seen = gen;
+    for (;;) {
+        cv.wait(lk, [&] { return stop || gen != seen; });
+        if (stop) return;
+        seen = gen;
+        int p;
+        while (take_part(&p)) {
+            const size_t lo = (size_t)p * part, len = std::min(part, bytes - lo);
+            unsigned char* d = dst;
+            const unsigned char* sp = src;
+            lk.unlock();
+            memcpy(d + lo, sp + lo, len);
+            lk.lock();
+            if (++finished == nparts) done_cv.notify_all();
+        }
+    }
+}
+
+void CopyPool::copy(void* d, const void* sv, size_t n) {
+    constexpr size_t kMin = 1u << 20;
+    if (n < kMin) {
+        memcpy(d, sv, n);
+        return;
+    }
+    std::lock_guard<std::mutex> jl(job_mu);
+    std::unique_lock<std::mutex> lk(mu);
+    if (workers.empty() && !stop) {
+        const unsigned hc = std::thread::hardware_concurrency();
+        const int nw = (int)std::max(1u, std::min(3u, hc > 1 ? hc / 2 : 1u));
+        for (int i = 0; i < nw; ++i) workers.emplace_back([this] { work(); });
+    }
+    const int parts = (int)workers.size() + 1;
+    dst = (unsigned char*)d;
+    src = (const unsigned char*)sv;
+    bytes = n;
+    part = ((n + parts - 1) / parts + 4095) & ~(size_t)4095;
+    nparts = (int)((n + part - 1) / part);
+    taken = 0;
+    finished = 0;
+    ++gen;
+    cv.notify_all();
+    int p;
+    while (take_part(&p)) {   // the caller copies parts too
+        const size_t lo = (size_t)p * part, len = std::min(part, n - lo);
+        lk.unlock();
+        memcpy(dst + lo, src + lo, len);
+        lk.lock();
+        ++finished;
+    }
+    done_cv.wait(lk, [&] { return finished == nparts; });
+}
+
+void CopyPool::shutdown() {
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        stop = true;
+    }
+    cv.notify_all();
+    for (std::thread& t : workers)
+        if (t.joinable()) t.join();
+    workers.clear();
+}
+
+// Host inputs to device memory through the lane's pinned staging buffer:
+// (dst, src, bytes) triples copied into consecutive 256-byte aligned slots of
+// the pinned buffer by the copy pool, then one DMA each on the lane's stream.
+// The staging buffer is reused only after the call that filled it has
+// synchronised its stream.
+static pa_status stage_to_device(Ctx* c, Lane& ln, void* const* dst, const void* const* src, const size_t* bytes,
+                                 int count) {
+    size_t total = 0;
+    for (int k = 0; k < count; ++k) total += (bytes[k] + 255) & ~(size_t)255;
+    pa_status st = ln.io_host.ensure(total);
+    if (st != PA_OK) return st;
+    size_t off = 0;
+    for (int k = 0; k < count; ++k) {
+        unsigned char* h = (unsigned char*)ln.io_host.ptr + off;
+        c->copier.copy(h, src[k], bytes[k]);
+        if (hipMemcpyAsync(dst[k], h, bytes[k], hipMemcpyHostToDevice, ln.stream) != hipSuccess) return PA_EDEVICE;
+        off += (bytes[k] + 255) & ~(size_t)255;
+    }
+    return PA_OK;
+}
+
+// Device outputs back to host memory through the pinned staging buffer
+// (synchronises the lane's stream).
+static pa_status stage_to_host(Ctx* c, Lane& ln, void* const* dst, const void* const* src, const size_t* bytes,
+                               int count) {
+    size_t total = 0;
+    for (int k = 0; k < count; ++k) total += (bytes[k] + 255) & ~(size_t)255;
+    pa_status st = ln.io_host.ensure(total);
+    if (st != PA_OK) return st;
+    size_t off = 0;
+    for (int k = 0; k < count; ++k) {
+        if (hipMemcpyAsync((unsigned char*)ln.io_host.ptr + off, src[k], bytes[k], hipMemcpyDeviceToHost,
+                           ln.stream) != hipSuccess)
+            return PA_EDEVICE;
+        off += (bytes[k] + 255) & ~(size_t)255;
+    }
+    if (hipStreamSynchronize(ln.stream) != hipSuccess) return PA_EDEVICE;
+    off = 0;
+    for (int k = 0; k < count; ++k) {
+        c->copier.copy(dst[k], (unsigned char*)ln.io_host.ptr + off, bytes[k]);
+        off += (bytes[k] + 255) & ~(size_t)255;
+    }
+    return PA_OK;
+}
+
+pa_status stage_in(Ctx* c, Lane& ln, void* const* dst, const void* const* src, const size_t* bytes, int count) {
+    return stage_to_device(c, ln, dst, src, bytes, count);
+}
+
 // ------------------------------------------------------------ twiddle tables
 
 bool Ctx::plan_cached(uint64_t n, uint64_t m, int policy, TilePlan* out) {
@@ -262,6 +384,7 @@ void Lane::release(Ctx* c) {
     if (stream) (void)hipStreamSynchronize(stream);   // the frees above are in its order
     meta_host.release();
     jobs_host.release();
+    io_host.release();
     timer.destroy();
     if (done) (void)hipEventDestroy(done);
     done = nullptr;
@@ -583,6 +706,7 @@ pa_status pa_create(pa_ctx** out, int device, uint64_t budget, void* hip_stream)
                pools != 0;
     (void)hipGetLastError();
     c->budget = budget ? budget : (8ull << 30);
+    c->cost = default_cost_model();
     if (hip_stream) {
         c->main.stream = (hipStream_t)hip_stream;
         c->main.own_stream = false;
@@ -611,6 +735,7 @@ void pa_destroy(pa_ctx* ctx) {
     for (Lane& ln : c->side) ln.release(c);
     c->serving_release();
     for (auto& kv : c->tabs) kv.second.buf.release(c);
+    c->copier.shutdown();
     delete c;
 }
 
@@ -640,9 +765,11 @@ pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, con
         pa_status s = ln.io.ensure(c, (sw + kw + ow) * 8, ln.stream);
         if (s != PA_OK) return s;
         uint64_t* base = (uint64_t*)ln.io.ptr;
-        if (hipMemcpyAsync(base, seed, sw * 8, hipMemcpyHostToDevice, ln.stream) != hipSuccess ||
-            hipMemcpyAsync(base + sw, key, kw * 8, hipMemcpyHostToDevice, ln.stream) != hipSuccess)
-            return PA_EDEVICE;
+        void* dsts[2] = {base, base + sw};
+        const void* srcs[2] = {seed, key};
+        const size_t lens[2] = {sw * 8, kw * 8};
+        s = stage_to_device(c, ln, dsts, srcs, lens, 2);
+        if (s != PA_OK) return s;
         dseed = base;
         dkey = base + sw;
         dout = base + sw + kw;
@@ -676,9 +803,10 @@ pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, con
         if (s == PA_OK && !async) s = ln.finish(c, flags, &st, nullptr);
     }
     if (s == PA_OK && !dev) {
-        if (hipMemcpyAsync(out, dout, ow * 8, hipMemcpyDeviceToHost, ln.stream) != hipSuccess ||
-            hipStreamSynchronize(ln.stream) != hipSuccess)
-            s = PA_EDEVICE;
+        void* dsts[1] = {out};
+        const void* srcs[1] = {dout};
+        const size_t lens[1] = {ow * 8};
+        s = stage_to_host(c, ln, dsts, srcs, lens, 1);
     }
     set_certified(&st, s);
     c->last = st;
@@ -778,6 +906,9 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
         if (s != PA_OK) return s;
     }
     uint64_t off = 0;
+    std::vector<void*> sdst;
+    std::vector<const void*> ssrc;
+    std::vector<size_t> slen;
     for (uint64_t i = 0; i < count; ++i) {
         const pa_job& j = jobs_in[i];
         const uint64_t *dseed = j.seed, *dkey = j.key;
@@ -785,9 +916,9 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
         if (!dev) {
             uint64_t* base = (uint64_t*)ln.io.ptr + off;
             const uint64_t sw = words_of(j.n + j.m - 1), kw = words_of(j.n), ow = words_of(j.m);
-            if (hipMemcpyAsync(base, j.seed, sw * 8, hipMemcpyHostToDevice, ln.stream) != hipSuccess ||
-                hipMemcpyAsync(base + sw, j.key, kw * 8, hipMemcpyHostToDevice, ln.stream) != hipSuccess)
-                return PA_EDEVICE;
+            sdst.insert(sdst.end(), {(void*)base, (void*)(base + sw)});
+            ssrc.insert(ssrc.end(), {(const void*)j.seed, (const void*)j.key});
+            slen.insert(slen.end(), {(size_t)(sw * 8), (size_t)(kw * 8)});
             dseed = base;
             dkey = base + sw;
             dout = base + sw + kw;
@@ -803,6 +934,10 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
         } else {
             fill_job(&all[i], dseed, dkey, dout, j.n, j.m, *plan_of[i]);
         }
+    }
+    if (!dev) {
+        const pa_status ss = stage_to_device(c, ln, sdst.data(), ssrc.data(), slen.data(), (int)sdst.size());
+        if (ss != PA_OK) return ss;
     }
     // One pipeline launch per length class.  The groups run concurrently on
     // the context's stream and on side streams (forked from it), largest
@@ -887,11 +1022,16 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
             if (status[i] == PA_OK) status[i] = s;
     }
     if (!dev && (s == PA_OK || s == PA_EPRECISION)) {
-        for (uint64_t i = 0; i < count; ++i)
-            if (hipMemcpyAsync(jobs_in[i].out, (uint64_t*)ln.io.ptr + out_off[i], words_of(ms[i]) * 8,
-                               hipMemcpyDeviceToHost, ln.stream) != hipSuccess)
-                s = PA_EDEVICE;
-        if (hipStreamSynchronize(ln.stream) != hipSuccess) s = PA_EDEVICE;
+        std::vector<void*> odst(count);
+        std::vector<const void*> osrc(count);
+        std::vector<size_t> olen(count);
+        for (uint64_t i = 0; i < count; ++i) {
+            odst[i] = jobs_in[i].out;
+            osrc[i] = (uint64_t*)ln.io.ptr + out_off[i];
+            olen[i] = words_of(ms[i]) * 8;
+        }
+        const pa_status os = stage_to_host(c, ln, odst.data(), osrc.data(), olen.data(), (int)count);
+        if (os != PA_OK) s = os;
     }
     if (per_job)
         for (uint64_t i = 0; i < count; ++i) per_job[i] = (s == PA_OK || s == PA_EPRECISION) ? status[i] : s;
@@ -912,7 +1052,7 @@ pa_status pa_plan_query(uint64_t n, uint64_t m, uint32_t flags, pa_plan* out) {
     if (!out || n == 0 || m == 0) return PA_EINVAL;
     const int policy = policy_of(flags);
     if (policy < 0) return PA_EINVAL;
-    CostModel cm;
+    const CostModel& cm = default_cost_model();
     TilePlan p;
     if (!plan_job(n, m, policy, cm, &p)) return PA_EINVAL;
     ClassGeom g;
@@ -951,9 +1091,11 @@ pa_status pa_hash_select(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t
         pa_status s = ln.io.ensure(c, (sw + kw) * 8, ln.stream);
         if (s != PA_OK) return s;
         uint64_t* base = (uint64_t*)ln.io.ptr;
-        if (hipMemcpyAsync(base, seed, sw * 8, hipMemcpyHostToDevice, ln.stream) != hipSuccess ||
-            hipMemcpyAsync(base + sw, key, kw * 8, hipMemcpyHostToDevice, ln.stream) != hipSuccess)
-            return PA_EDEVICE;
+        void* dsts[2] = {base, base + sw};
+        const void* srcs[2] = {seed, key};
+        const size_t lens[2] = {sw * 8, kw * 8};
+        s = stage_to_device(c, ln, dsts, srcs, lens, 2);
+        if (s != PA_OK) return s;
         dseed = base;
         dkey = base + sw;
     }

@@ -44,6 +44,31 @@ struct HostBuf {
     void release();
 };
 
+// Copies from pageable host memory into pinned staging buffers (and back),
+// split over a few host threads: one thread reads pageable memory at a few
+// GB/s, well below what the DMA engines take from pinned memory.  Jobs below
+// 1 MiB are copied by the caller alone.  Threads start at the first large
+// copy and stop when the context is destroyed.
+struct CopyPool {
+    std::mutex mu;
+    std::condition_variable cv, done_cv;
+    std::vector<std::thread> workers;
+    unsigned char* dst = nullptr;
+    const unsigned char* src = nullptr;
+    size_t bytes = 0, part = 0;
+    int nparts = 0, taken = 0, finished = 0;
+    uint64_t gen = 0;
+    bool stop = false;
+    std::mutex job_mu;   // one copy job at a time
+    void copy(void* d, const void* s, size_t n);
+    void shutdown();
+    ~CopyPool() { shutdown(); }
+
+  private:
+    void work();
+    bool take_part(int* p);
+};
+
 struct DevTables {
     DevBuf buf;
     Tables t;
@@ -68,6 +93,7 @@ struct Lane {
     DevBuf ws, part, meta, jobs_dev, io;
     DevBuf aux;           // direct path: reversed key, selected indices and bits
     HostBuf meta_host, jobs_host;
+    HostBuf io_host;      // pinned staging of host inputs and outputs
     PassTimer timer;
     bool static_tables = false;   // twiddle tables from the no-allocation entry's array
 
@@ -124,6 +150,7 @@ struct Ctx {
     bool plan_cached(uint64_t n, uint64_t m, int policy, TilePlan* out);
     bool pools = false;   // stream-ordered allocation supported on the device
     pa_stats last{};
+    CopyPool copier;
 
     pa_status tables(int prec, int cls, Tables* out);
 
@@ -156,6 +183,10 @@ void set_certified(pa_stats* s, pa_status st);
 void fill_job(JobDesc* jd, const uint64_t* seed, const uint64_t* key, uint64_t* out, uint64_t n, uint64_t m,
               const TilePlan& p);
 double now_seconds();
+// Host buffers to device memory on a lane's stream through its pinned staging
+// buffer (copied in by the context's copy pool, then one DMA each); the lane's
+// stream must be synchronised before the staging buffer is used again.
+pa_status stage_in(Ctx* c, Lane& ln, void* const* dst, const void* const* src, const size_t* bytes, int count);
 pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path);
 pa_status tune_load(Ctx* c, const char* path);
 

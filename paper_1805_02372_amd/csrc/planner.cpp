@@ -7,10 +7,14 @@
 
 #include "pa.h"
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <string>
 
 namespace pa {
 
@@ -199,6 +203,7 @@ CostModel::CostModel() {
     // two VALU operations per output and key word at half the vector rate
     // (256 CUs x 64 lanes x 2.4 GHz)
     direct_s = 1.0e-13;
+    direct_launch_s = 12e-6;
     for (int p = 0; p < 3; ++p)
         for (int id = 0; id < 64; ++id) {
             const uint64_t Lc = class_len(id);
@@ -216,15 +221,99 @@ CostModel::CostModel() {
             // MI355X: about 1.8x in FP32 and 1.4x in FP64)
             const double generic = (id >= 32 && Lc >= (1ull << 20)) ? (p == 1 ? 1.4 : 1.8) : 1.0;
             tile_s[p][id] = generic * std::max(t_mem, t_alu) + 1e-6;
+            first_s[p][id] = launch_s;
         }
 }
 
 double CostModel::tile(int prec, int cls) const { return tile_s[prec_index(prec)][cls]; }
+double CostModel::first(int prec, int cls) const { return first_s[prec_index(prec)][cls]; }
 void CostModel::set(int prec, int cls, double s) { tile_s[prec_index(prec)][cls] = s; }
+void CostModel::set_first(int prec, int cls, double s) { first_s[prec_index(prec)][cls] = s; }
+
+static const char* prec_key(int prec) { return prec == PREC_FP32 ? "fp32" : prec == PREC_FP64 ? "fp64" : "ntt"; }
+
+// Minimal reader of the table pa_tune writes:
+//   {"launch": s, "direct": s, "direct_launch": s,
+//    "fp32": {"<L>": [tile_s, first_s], ...}, "fp64": {...}}
+// (a plain number instead of the pair sets tile_s only).
+int load_tune_table(CostModel& cm, const char* path) {
+    FILE* f = fopen(path, "r");
+    if (!f) return -1;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    fclose(f);
+    int loaded = 0;
+    const size_t la = text.find("\"launch\":");
+    if (la != std::string::npos) {
+        const double v = strtod(text.c_str() + la + 9, nullptr);
+        if (v >= 0 && v < 1.0) cm.launch_s = v;
+    }
+    const size_t di = text.find("\"direct\":");
+    if (di != std::string::npos) {
+        const double v = strtod(text.c_str() + di + 9, nullptr);
+        if (v > 0 && v < 1e-6) {
+            cm.direct_s = v;
+            ++loaded;
+        }
+    }
+    const size_t dl = text.find("\"direct_launch\":");
+    if (dl != std::string::npos) {
+        const double v = strtod(text.c_str() + dl + 16, nullptr);
+        if (v >= 0 && v < 1e-2) cm.direct_launch_s = v;
+    }
+    for (int prec : {PREC_FP32, PREC_FP64, PREC_NTT}) {
+        const std::string tag = std::string("\"") + prec_key(prec) + "\"";
+        const size_t at = text.find(tag);
+        if (at == std::string::npos) continue;
+        const size_t open = text.find('{', at), close = text.find('}', at);
+        if (open == std::string::npos || close == std::string::npos || close < open) return -1;
+        const std::string body = text.substr(open + 1, close - open - 1);
+        for (int k = kMinClassId; k <= kMaxClassId; ++k) {
+            ClassGeom g;
+            if (!class_geometry(prec, k, &g)) continue;
+            const std::string key = "\"" + std::to_string(g.L) + "\":";
+            const size_t p = body.find(key);
+            if (p == std::string::npos) continue;
+            const char* q = body.c_str() + p + key.size();
+            while (*q == ' ') ++q;
+            const bool pair = *q == '[';
+            char* end = nullptr;
+            const double v = strtod(pair ? q + 1 : q, &end);
+            if (!(v > 0 && v < 10.0)) continue;
+            cm.set(prec, k, v);
+            ++loaded;
+            if (pair && end) {
+                while (*end == ' ' || *end == ',') ++end;
+                const double w = strtod(end, nullptr);
+                if (w >= 0 && w < 1.0) cm.set_first(prec, k, w);
+            }
+        }
+    }
+    return loaded;
+}
+
+const CostModel& default_cost_model() {
+    static const CostModel cm = [] {
+        CostModel m;
+        const char* e = getenv("PA_TUNE_DEFAULT");
+        if (e && e[0] == '0') return m;
+        Dl_info info;
+        if (dladdr((const void*)&load_tune_table, &info) && info.dli_fname) {
+            std::string dir(info.dli_fname);
+            const size_t slash = dir.rfind('/');
+            dir = slash == std::string::npos ? std::string(".") : dir.substr(0, slash);
+            (void)load_tune_table(m, (dir + "/tune_mi355x.json").c_str());
+        }
+        return m;
+    }();
+    return cm;
+}
 
 double direct_cost(uint64_t n, uint64_t m, const CostModel& cm) {
     const double outs = (double)(ceil_div(m, 256) * 256), words = (double)(ceil_div(ceil_div(n, 32), 4) * 4);
-    return cm.launch_s + cm.direct_s * outs * words;
+    return cm.direct_launch_s + cm.direct_s * outs * words;
 }
 
 bool choose_direct(uint32_t flags, uint64_t n, uint64_t m, const CostModel& cm, const TilePlan& fft) {
@@ -279,7 +368,7 @@ bool plan_at_class(uint64_t n, uint64_t m, int prec, int cls, const CostModel& c
     best.bound = error_bound(prec, L, best.Bi);
     best.rigorous = rigorous_bound(prec, L, best.Bi, best.Bo);
     if (best.bound > kPlanErrorLimit) return false;   // not reached by FP32 up to 2^24
-    best.cost = (double)best.tiles() * cm.tile(prec, cls) + cm.launch_s;
+    best.cost = (double)best.tiles() * cm.tile(prec, cls) + cm.first(prec, cls);
     *out = best;
     return true;
 }
@@ -289,15 +378,23 @@ bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan*
     const int prec = policy;
     int ids[kMaxClassId + 1];
     const int nid = class_ids(prec, ids, cap_logL);
+    // Classes come in increasing length.  A plan that moves more points (tiles
+    // x L) replaces the best so far only when its modeled cost is lower by
+    // more than the noise of the measured costs (10%), so near-ties keep the
+    // plan with fewer bytes.
+    auto better = [](const TilePlan& p, const TilePlan& best) {
+        const double pts = (double)p.tiles() * (double)p.L, bpts = (double)best.tiles() * (double)best.L;
+        return pts <= bpts ? p.cost < best.cost : p.cost < 0.9 * best.cost;
+    };
     if (prec == PREC_FP64 || prec == PREC_NTT) {
-        // one tile: the cheapest class that holds the whole product (the
-        // shortest one unless a longer class runs faster kernels)
+        // one tile: the shortest class that holds the whole product, unless a
+        // longer class is clearly cheaper
         bool one = false;
         TilePlan best1;
         for (int q = 0; q < nid; ++q) {
             TilePlan p;
             if (n + m - 1 > class_len(ids[q]) || !plan_at_class(n, m, prec, ids[q], cm, &p)) continue;
-            if (!one || p.cost < best1.cost) {
+            if (!one || better(p, best1)) {
                 best1 = p;
                 one = true;
             }
@@ -312,7 +409,7 @@ bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan*
     for (int q = 0; q < nid; ++q) {
         TilePlan p;
         if (!plan_at_class(n, m, prec, ids[q], cm, &p)) continue;
-        if (!found || p.cost < best.cost) {
+        if (!found || better(p, best)) {
             best = p;
             found = true;
         }
@@ -346,11 +443,11 @@ bool plan_batch_groups(const std::vector<uint64_t>& ns, const std::vector<uint64
         g.cls = p.cls;
         g.jobs.push_back(i);
         g.plans.push_back(p);
-        g.cost += p.cost - cm.launch_s;
+        g.cost += p.cost - cm.first(policy, p.cls);
     }
     std::vector<BatchGroup> gs;
     for (auto& kv : by_class) {
-        kv.second.cost += cm.launch_s;
+        kv.second.cost += cm.first(policy, kv.second.cls);
         gs.push_back(std::move(kv.second));
     }
     // fold groups while that saves more than it costs
@@ -367,7 +464,7 @@ bool plan_batch_groups(const std::vector<uint64_t>& ns, const std::vector<uint64
                 for (size_t q = 0; q < gs[g].jobs.size() && ok; ++q) {
                     const size_t i = gs[g].jobs[q];
                     ok = at_class(i, gs[h].cls, &moved[q]);
-                    c += moved[q].cost - cm.launch_s;
+                    c += moved[q].cost - cm.first(policy, gs[h].cls);
                 }
                 if (!ok) continue;
                 const double gain = gs[g].cost - c;   // the launch of g disappears
@@ -383,7 +480,7 @@ bool plan_batch_groups(const std::vector<uint64_t>& ns, const std::vector<uint64
         for (size_t q = 0; q < gs[bg].jobs.size(); ++q) {
             h.jobs.push_back(gs[bg].jobs[q]);
             h.plans.push_back(best_plans[q]);
-            h.cost += best_plans[q].cost - cm.launch_s;
+            h.cost += best_plans[q].cost - cm.first(policy, h.cls);
         }
         gs.erase(gs.begin() + (long)bg);
     }
@@ -403,11 +500,11 @@ bool plan_batch(const std::vector<uint64_t>& ns, const std::vector<uint64_t>& ms
     const int nid = class_ids(policy, ids);
     for (int q = 0; q < nid; ++q) {
         const int k = ids[q];
-        double cost = cm.launch_s;
+        double cost = cm.first(policy, k);
         bool ok = true;
         for (size_t i = 0; i < ns.size() && ok; ++i) {
             ok = plan_at_class(ns[i], ms[i], policy, k, cm, &tmp[i]);
-            if (ok) cost += tmp[i].cost - cm.launch_s;
+            if (ok) cost += tmp[i].cost - cm.first(policy, k);
         }
         if (!ok) continue;
         if (!found || cost < best_cost) {

@@ -32,16 +32,30 @@ int class_ids(int prec, int* ids, int cap_logL = 24);
 // A key of the environment settings above (plan caches depend on them).
 uint64_t class_filter_key();
 
-// Cost per tile (seconds) of a class, by prec and class id.  Filled from
-// tuning data when present, else from the built-in model.
+// Cost of a class's launches (seconds), by prec and class id: a launch of T
+// tiles costs first_s + T tile_s.  tile_s is the marginal cost of a tile on a
+// full device; first_s the rest of a one-tile launch (launch latency, ramp-up,
+// and the part of the device one tile leaves idle).  Filled from tuning data
+// when present, else from the built-in model.
 struct CostModel {
     double tile_s[3][64];   // [0] FP32, [1] FP64, [2] NTT; index class id
-    double launch_s;        // fixed cost of one pipeline launch
+    double first_s[3][64];  // extra cost of a launch (its first tile)
+    double launch_s;        // launch cost of a class without its own first_s
     double direct_s;        // direct GF(2) path: seconds per output per 32-bit key word
+    double direct_launch_s; // direct GF(2) path: fixed cost of a job (its two launches)
     CostModel();
     double tile(int prec, int cls) const;
+    double first(int prec, int cls) const;
     void set(int prec, int cls, double s);
+    void set_first(int prec, int cls, double s);
 };
+// The model a context starts from: the built-in one, replaced class by class
+// by the tuning table measured on MI355X that ships beside the library
+// (tune_mi355x.json next to libpa.so; PA_TUNE_DEFAULT=0 skips it).
+const CostModel& default_cost_model();
+// Read a tuning table (pa_tune's JSON) into cm; returns the number of values
+// taken, or -1 if the file cannot be read.
+int load_tune_table(CostModel& cm, const char* path);
 
 struct TilePlan {
     int prec = 0, cls = 0;
@@ -84,9 +98,10 @@ bool choose_direct(uint32_t flags, uint64_t n, uint64_t m, const CostModel& cm, 
 bool plan_at_class(uint64_t n, uint64_t m, int prec, int cls, const CostModel& cm, TilePlan* out);
 
 // Best plan over classes for one job.  policy: PREC_FP32 (segmented, bound
-// limited), PREC_FP64 and PREC_NTT (the cheapest single tile if one fits, else
-// the cheapest plan over the classes).  Classes longer than 2^cap_logL are not
-// used.
+// limited), PREC_FP64 and PREC_NTT (a single tile if one fits, else the
+// cheapest plan over the classes).  Among plans whose modeled costs differ by
+// less than 10% the one that moves fewer points wins.  Classes longer than
+// 2^cap_logL are not used.
 bool plan_job(uint64_t n, uint64_t m, int policy, const CostModel& cm, TilePlan* out, int cap_logL = 24);
 
 // Jobs of a batch that share one FFT length class (one pipeline launch).
@@ -94,7 +109,7 @@ struct BatchGroup {
     int cls = 0;
     std::vector<size_t> jobs;      // indices into the batch
     std::vector<TilePlan> plans;   // plan of each job in `jobs`, at class cls
-    double cost = 0;               // launch plus tiles
+    double cost = 0;               // launch (first_s) plus tiles
 };
 
 // Batch plan with one launch per length class: every job starts in its own

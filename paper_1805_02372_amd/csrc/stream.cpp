@@ -66,9 +66,13 @@ pa_status pa_stream_feed(pa_stream* s, const uint64_t* key_block, uint64_t lo, u
             pa_status st = s->in.ensure(c, (sw + kw) * 8, c->main.stream);
             if (st != PA_OK) return st;
             uint64_t* base = (uint64_t*)s->in.ptr;
-            if (hipMemcpyAsync(base, seed_block, sw * 8, hipMemcpyHostToDevice, c->main.stream) != hipSuccess ||
-                hipMemcpyAsync(base + sw, key_block, kw * 8, hipMemcpyHostToDevice, c->main.stream) != hipSuccess)
-                return PA_EDEVICE;
+            void* dsts[2] = {base, base + sw};
+            const void* srcs[2] = {seed_block, key_block};
+            const size_t lens[2] = {sw * 8, kw * 8};
+            st = stage_in(c, c->main, dsts, srcs, lens, 2);   // pinned staging, multi-threaded copy
+            // the staging buffer is the context's: the copies land before the lock is released
+            if (st == PA_OK && hipStreamSynchronize(c->main.stream) != hipSuccess) st = PA_EDEVICE;
+            if (st != PA_OK) return st;
             dseed = base;
             dkey = base + sw;
         }

@@ -26,69 +26,26 @@ static uint64_t xorshift(uint64_t& s) {
 
 static const char* prec_key(int prec) { return prec == PREC_FP32 ? "fp32" : prec == PREC_FP64 ? "fp64" : "ntt"; }
 
+// {"launch": s, "direct": s, "direct_launch": s, "fp32": {"<L>": [tile_s, first_s], ...}, ...}
 static pa_status save_json(const CostModel& cm, const std::vector<int>& precs, const char* path) {
     FILE* f = fopen(path, "w");
     if (!f) return PA_EINVAL;
-    fprintf(f, "{\"launch\": %.9g, \"direct\": %.9g", cm.launch_s, cm.direct_s);
+    fprintf(f, "{\"launch\": %.9g, \"direct\": %.9g, \"direct_launch\": %.9g", cm.launch_s, cm.direct_s,
+            cm.direct_launch_s);
     for (size_t i = 0; i < precs.size(); ++i) {
         fprintf(f, ", \"%s\": {", prec_key(precs[i]));
         bool first = true;
         for (int k = kMinClassId; k <= kMaxClassId; ++k) {
             ClassGeom g;
             if (!class_geometry(precs[i], k, &g)) continue;
-            fprintf(f, "%s\"%llu\": %.9g", first ? "" : ", ", (unsigned long long)g.L, cm.tile(precs[i], k));
+            fprintf(f, "%s\"%llu\": [%.9g, %.9g]", first ? "" : ", ", (unsigned long long)g.L, cm.tile(precs[i], k),
+                    cm.first(precs[i], k));
             first = false;
         }
         fprintf(f, "}");
     }
     fprintf(f, "}\n");
     return fclose(f) == 0 ? PA_OK : PA_EINVAL;
-}
-
-// Minimal reader for the format save_json writes.
-static pa_status load_json(CostModel& cm, const char* path) {
-    FILE* f = fopen(path, "r");
-    if (!f) return PA_EINVAL;
-    std::string text;
-    char buf[4096];
-    size_t got;
-    while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
-    fclose(f);
-    int loaded = 0;
-    const size_t la = text.find("\"launch\":");
-    if (la != std::string::npos) {
-        const double v = strtod(text.c_str() + la + 9, nullptr);
-        if (v >= 0 && v < 1.0) cm.launch_s = v;
-    }
-    const size_t di = text.find("\"direct\":");
-    if (di != std::string::npos) {
-        const double v = strtod(text.c_str() + di + 9, nullptr);
-        if (v > 0 && v < 1e-6) {
-            cm.direct_s = v;
-            ++loaded;
-        }
-    }
-    for (int prec : {PREC_FP32, PREC_FP64, PREC_NTT}) {
-        const std::string tag = std::string("\"") + prec_key(prec) + "\"";
-        size_t at = text.find(tag);
-        if (at == std::string::npos) continue;
-        const size_t open = text.find('{', at), close = text.find('}', at);
-        if (open == std::string::npos || close == std::string::npos || close < open) return PA_EINVAL;
-        const std::string body = text.substr(open + 1, close - open - 1);
-        for (int k = kMinClassId; k <= kMaxClassId; ++k) {
-            ClassGeom g;
-            if (!class_geometry(prec, k, &g)) continue;
-            const std::string key = "\"" + std::to_string(g.L) + "\":";
-            size_t p = body.find(key);
-            if (p == std::string::npos) continue;
-            const double v = strtod(body.c_str() + p + key.size(), nullptr);
-            if (v > 0 && v < 10.0) {
-                cm.set(prec, k, v);
-                ++loaded;
-            }
-        }
-    }
-    return loaded ? PA_OK : PA_EINVAL;
 }
 
 // Kernel time (s) of one launch of `count` identical one-tile jobs of class id k.
@@ -111,9 +68,10 @@ static pa_status time_launch(Ctx* c, int prec, int k, const TilePlan& p, int cou
 }
 
 // Per class: kernel time of one launch with 1 tile (T1) and with 4 tiles (T4);
-// the marginal tile cost (T4 - T1) / 3 goes to the class, the rest (T1 minus
-// one tile: ramp-up and tail of the launch) to the per-launch cost (median
-// over the classes measured).
+// the marginal tile cost (T4 - T1) / 3 goes to the class's tile_s, the rest of
+// T1 (ramp-up and tail of the launch, and what one tile leaves of the device
+// idle) to its first_s; the median of the latter is the launch cost of the
+// direct path.
 pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path) {
     std::vector<int> precs;
     switch (flags & PA_PREC_MASK) {
@@ -166,6 +124,7 @@ pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path) {
             if (t1 >= 1e30 || t4 >= 1e30) continue;
             const double marginal = std::max((t4 - t1) / (kMany - 1), 0.1 * t1);
             cm.set(prec, k, marginal);
+            cm.set_first(prec, k, std::max(t1 - marginal, 0.0));
             fixed.push_back(std::max(t1 - marginal, 0.0));
         }
     }
@@ -191,7 +150,10 @@ pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path) {
         }
         const double words = (double)((n / 32 + 3) / 4 * 4);
         const double slope = (t[1] - t[0]) / ((double)(ms[1] - ms[0]) * words);
-        if (t[1] < 1e30 && slope > 0) cm.direct_s = slope;
+        if (t[1] < 1e30 && slope > 0) {
+            cm.direct_s = slope;
+            cm.direct_launch_s = std::max(t[0] - slope * (double)ms[0] * words, 0.0);   // the intercept
+        }
     }
     buf.release(c);
     if (!fixed.empty()) {
@@ -210,12 +172,10 @@ pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path) {
 pa_status tune_load(Ctx* c, const char* path) {
     std::lock_guard<std::mutex> lk(c->plan_mu);
     CostModel cm = c->cost;
-    const pa_status st = load_json(cm, path);
-    if (st == PA_OK) {
-        c->cost = cm;
-        c->plans.clear();
-    }
-    return st;
+    if (load_tune_table(cm, path) <= 0) return PA_EINVAL;
+    c->cost = cm;
+    c->plans.clear();
+    return PA_OK;
 }
 
 }  // namespace pa

@@ -107,20 +107,27 @@ def test_batch_invalid_job(pa, ctx):
 
 # --------------------------------------------------- precision certificate
 
-def test_fp32_certificate_falls_back_on_all_ones_seed(pa, ctx):
-    """An all-ones seed makes the +-1 encoded spectrum a huge DC term; FP32
-    tiles fail their certificate and are re-run in FP64.  Closed form: every
-    output is the parity of the key's weight."""
+def test_fp32_certificate_falls_back_on_all_ones_seed(pa, ctx, monkeypatch):
+    """An all-ones seed makes the +-1 encoded spectrum a huge DC term, and
+    every window value equals the chunk's weight.  With chunks of 3 * 10^6 bits
+    (classes from 2^22 on) that weight is above what the FP32 certificate
+    accepts, so the tiles are re-run in FP64; with the plan the cost model
+    picks (shorter chunks) the result must be exact either way.  Closed form:
+    every output is the parity of the key's weight."""
     from gpu_util import gpu_hash
     rng = np.random.default_rng(21)
     n, m = 3_000_000, 100_000
     seed = synth.pattern_bits("ones", n + m - 1)
     key = synth.gen_bits(rng, n)
+    par = int(np.unpackbits(key.view(np.uint8)).sum()) & 1
+    st, y = gpu_hash(pa, ctx, seed, n, m, key, pa.PA_PREC_FP32_SEG)
+    assert st == pa.PA_OK
+    assert np.array_equal(synth.bits_to_array(y, m), np.full(m, par, np.uint8)), pa.pa_last_stats(ctx)
+    monkeypatch.setenv("PA_MIN_LOG2_LEN", "22")
     st, y = gpu_hash(pa, ctx, seed, n, m, key, pa.PA_PREC_FP32_SEG)
     assert st == pa.PA_OK
     s = pa.pa_last_stats(ctx)
-    assert s["fallback_tiles"] > 0, s
-    par = int(np.unpackbits(key.view(np.uint8)).sum()) & 1
+    assert s["fallback_tiles"] > 0 and s["chunk_bits"] > (1 << 21), s
     assert np.array_equal(synth.bits_to_array(y, m), np.full(m, par, np.uint8))
     st2, _ = gpu_hash(pa, ctx, seed, n, m, key, pa.PA_PREC_FP32_SEG | pa.PA_NO_FALLBACK)
     assert st2 == pa.PA_EPRECISION
@@ -135,6 +142,7 @@ def test_fallback_rebuilds_accumulated_job(pa, ctx, monkeypatch):
     A random job in the same batch keeps its FP32 result."""
     from gpu_util import to_dev, from_dev, empty_dev
     monkeypatch.setenv("PA_MAX_LOG2_LEN", "21")
+    monkeypatch.setenv("PA_MIN_LOG2_LEN", "21")   # chunks of about 1.8 * 10^6 bits: weights above 2^20
     rng = np.random.default_rng(22)
     n, m = 3_000_001, 300_000
     seed = synth.pattern_bits("ones", n + m - 1)
@@ -332,10 +340,11 @@ def test_tune_writes_and_loads(pa, ctx, tmp_path):
     # keyed by FFT length: every class, power-of-two and mixed-radix
     lens = sorted(int(k) for k in data["fp32"])
     assert {1 << k for k in range(12, 25)} <= set(lens) and {3 << 22, 5 << 21, 7 << 21} <= set(lens)
+    # per class: [marginal cost of a tile, rest of a one-tile launch]
     costs = [data["fp32"][str(L)] for L in lens]
-    assert all(c > 0 for c in costs)
+    assert all(c[0] > 0 and c[1] >= 0 for c in costs)
     assert 0 <= data["launch"] < 1e-2   # per-launch cost in seconds
-    assert costs[-1] > costs[0]          # longer transforms cost more
+    assert costs[-1][0] > costs[0][0]    # longer transforms cost more
     c2 = pa.pa_create(0, 0, None)
     try:
         assert pa.pa_tune_load(c2, path) == pa.PA_OK

@@ -200,13 +200,15 @@ def test_serving_stream_at_scale(pa):
         pa.pa_destroy(c)
 
 
-def test_serving_fallback_in_batch(pa):
+def test_serving_fallback_in_batch(pa, monkeypatch):
     """A request on an all-ones seed gives |z| = weight of its key chunk, above
     what the FP32 certificate accepts (2^20), so its tiles are re-run in FP64
     inside the serving batch it shares with random requests.  All-ones seed:
     every output is the parity of the key's weight (a closed form)."""
     import torch
     from gpu_util import to_dev, empty_dev, from_dev
+    # classes from 2^22 on: the all-ones requests' chunks weigh more than 2^20
+    monkeypatch.setenv("PA_MIN_LOG2_LEN", "22")
     rng = np.random.default_rng(2718)
     seed_bits = 30_000_000
     ones = synth.pattern_bits("ones", seed_bits)

@@ -247,7 +247,11 @@ def test_rigorous_bound_fp64_margin_and_monotone(pa):
     prev = 0.0
     for k in range(12, 25):
         n = (1 << k) // 2
-        p = pa.pa_plan_query(n, n, pa.PA_PREC_FP64)
+        os.environ["PA_MAX_LOG2_LEN"] = str(k)   # 2^k is then the only class that holds n + n - 1 bits
+        try:
+            p = pa.pa_plan_query(n, n, pa.PA_PREC_FP64)
+        finally:
+            del os.environ["PA_MAX_LOG2_LEN"]
         assert p["log2_len"] == k and p["chunks"] == 1
         assert 0 < p["rigorous_bound"] < 1e-4, p      # 5000x below the rounding margin 0.5
         assert p["rigorous_bound"] > prev
@@ -312,3 +316,34 @@ def test_class_filters(pa, monkeypatch):
     for f in (pa.PA_PREC_FP32_SEG, pa.PA_PREC_FP64):
         p = pa.pa_plan_query(1_000_000, 300_000, f)
         assert p["fft_len"] == 3 << 16 and p["chunks"] * p["windows"] > 1, p
+
+
+def test_shipped_tuning_table(pa):
+    """The cost table measured on MI355X (pa_tune, one- and four-tile launches
+    per class) ships beside libpa.so and covers every class: per class the
+    marginal cost of a tile and the rest of a one-tile launch."""
+    import json
+    path = os.path.join(os.path.dirname(pa.LIB_PATH), "tune_mi355x.json")
+    t = json.load(open(path))
+    assert 0 < t["launch"] < 1e-3 and 0 < t["direct"] < 1e-9
+    for prec, lens in (("fp32", CLASS_LENS), ("fp64", CLASS_LENS), ("ntt", {1 << k for k in range(12, 25)})):
+        assert {int(k) for k in t[prec]} == lens, prec
+        for L, (tile, first) in t[prec].items():
+            assert 0 < tile < 0.1 and 0 <= first < 0.01, (prec, L, tile, first)
+
+
+def test_plans_from_the_shipped_table_stay_valid(pa):
+    """With the shipped table or the built-in model (PA_TUNE_DEFAULT=0, in a
+    process of its own), every plan satisfies the tiling invariants."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r); from paper_1805_02372_amd import pa; "
+            "print([pa.pa_plan_query(n, m, f)['fft_len'] for n, m in [(131072, 16384), (1000000, 200000), "
+            "(12345679, 1234567)] for f in (0, 0x20)])") % ROOT
+    out = {}
+    for v in ("1", "0"):
+        env = dict(os.environ, PA_TUNE_DEFAULT=v)
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
+        assert r.returncode == 0, r.stderr[-2000:]
+        out[v] = eval(r.stdout.strip().splitlines()[-1])
+        assert all(L in CLASS_LENS for L in out[v])
