@@ -326,7 +326,9 @@ typedef struct {
 } pa_plan;
 
 /* The plan pa_hash would use for (n, m) under the precision bits of flags,
- * with the built-in cost model (no tuning data, no device).  Tile k (chunk b =
+ * with the starting cost model of a new context (the MI355X table shipped
+ * beside the library, or the built-in model when PA_TUNE_DEFAULT=0; no
+ * pa_tune data, no device).  Tile k (chunk b =
  * k / windows, window o = k % windows) covers key bits [max(0, n-(b+1)Bi),
  * n-b*Bi) and outputs [o*Bo, min(m, (o+1)*Bo)). */
 pa_status pa_plan_query(uint64_t n, uint64_t m, uint32_t flags, pa_plan* plan);

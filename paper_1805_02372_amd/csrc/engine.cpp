@@ -863,27 +863,50 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
         std::lock_guard<std::mutex> pk(c->plan_mu);
         cm = c->cost;
     }
-    // jobs on the direct path, and the FFT jobs (planned in length-class groups)
-    std::vector<char> is_direct(count, 0);
-    std::vector<uint64_t> fns, fms;
-    std::vector<size_t> fidx;
-    std::vector<TilePlan> fplans;
+    // jobs on the direct path, and the FFT jobs (planned in length-class
+    // groups); a batch of the same shapes as a recent one reuses its plan
+    std::vector<uint64_t> shapes(2 * count);
     for (uint64_t i = 0; i < count; ++i) {
-        TilePlan p;
-        if (!c->plan_cached(ns[i], ms[i], policy, &p)) return PA_EINVAL;
-        is_direct[i] = choose_direct(flags, ns[i], ms[i], cm, p);
-        if (!is_direct[i]) {
-            fidx.push_back(i);
-            fns.push_back(ns[i]);
-            fms.push_back(ms[i]);
-            fplans.push_back(p);
+        shapes[2 * i] = ns[i];
+        shapes[2 * i + 1] = ms[i];
+    }
+    auto bkey = std::make_tuple(policy, flags & PA_PREC_MASK, class_filter_key(), std::move(shapes));
+    std::vector<char> is_direct;
+    std::vector<BatchGroup> groups;
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> pk(c->plan_mu);
+        auto it = c->batch_plans.find(bkey);
+        if (it != c->batch_plans.end()) {
+            is_direct = it->second.is_direct;
+            groups = it->second.groups;
+            cached = true;
         }
     }
-    std::vector<BatchGroup> groups;
-    if (!fidx.empty()) {
-        if (!plan_batch_groups(fns, fms, policy, cm, &groups, &fplans)) return PA_EINVAL;
-        for (BatchGroup& g : groups)
-            for (size_t& q : g.jobs) q = fidx[q];
+    if (!cached) {
+        is_direct.assign(count, 0);
+        std::vector<uint64_t> fns, fms;
+        std::vector<size_t> fidx;
+        std::vector<TilePlan> fplans;
+        for (uint64_t i = 0; i < count; ++i) {
+            TilePlan p;
+            if (!c->plan_cached(ns[i], ms[i], policy, &p)) return PA_EINVAL;
+            is_direct[i] = choose_direct(flags, ns[i], ms[i], cm, p);
+            if (!is_direct[i]) {
+                fidx.push_back(i);
+                fns.push_back(ns[i]);
+                fms.push_back(ms[i]);
+                fplans.push_back(p);
+            }
+        }
+        if (!fidx.empty()) {
+            if (!plan_batch_groups(fns, fms, policy, cm, &groups, &fplans)) return PA_EINVAL;
+            for (BatchGroup& g : groups)
+                for (size_t& q : g.jobs) q = fidx[q];
+        }
+        std::lock_guard<std::mutex> pk(c->plan_mu);
+        if (c->batch_plans.size() >= 16) c->batch_plans.clear();
+        c->batch_plans[std::move(bkey)] = Ctx::BatchPlan{is_direct, groups};
     }
     std::vector<const TilePlan*> plan_of(count, nullptr);
     pa_stats st{};
@@ -957,7 +980,7 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
     }
     // direct jobs on the context's stream, beside the side streams' groups
     pa_stats dst{};
-    const size_t ndirect = count - fidx.size();
+    const size_t ndirect = (size_t)std::count(is_direct.begin(), is_direct.end(), (char)1);
     for (uint64_t i = 0; i < count && s == PA_OK; ++i) {
         if (!is_direct[i]) continue;
         const pa_status ds = ln.direct(c, all[i].seed, all[i].key, all[i].n, all[i].m, all[i].out, false, &dst);
@@ -1007,7 +1030,7 @@ pa_status pa_hash_batch(pa_ctx* ctx, const pa_job* jobs_in, uint64_t count, uint
     if (ndirect && hipStreamSynchronize(ln.stream) != hipSuccess && s == PA_OK) s = PA_EDEVICE;
     lst.push_back(dst);
     st.direct_jobs = dst.direct_jobs;
-    if (fidx.empty()) st.prec = PA_PREC_DIRECT;
+    if (ndirect == count) st.prec = PA_PREC_DIRECT;
     for (const pa_stats& x : lst) {
         st.model_bytes += x.model_bytes;
         st.tiles += x.tiles;

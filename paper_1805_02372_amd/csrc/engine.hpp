@@ -148,6 +148,18 @@ struct Ctx {
     std::mutex plan_mu;
     std::map<std::tuple<uint64_t, uint64_t, int, uint64_t>, TilePlan> plans;
     bool plan_cached(uint64_t n, uint64_t m, int policy, TilePlan* out);
+    // Plans of recent batches: which jobs take the direct path and the
+    // length-class groups of the others.  Key: policy, precision flags, class
+    // filter, then n and m of every job in order.  Cleared with `plans`.
+    struct BatchPlan {
+        std::vector<char> is_direct;
+        std::vector<BatchGroup> groups;
+    };
+    std::map<std::tuple<int, uint32_t, uint64_t, std::vector<uint64_t>>, BatchPlan> batch_plans;
+    void cost_changed() {   // with plan_mu held
+        plans.clear();
+        batch_plans.clear();
+    }
     bool pools = false;   // stream-ordered allocation supported on the device
     pa_stats last{};
     CopyPool copier;

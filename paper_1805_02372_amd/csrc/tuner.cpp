@@ -163,7 +163,7 @@ pa_status tune_context(Ctx* c, uint32_t flags, int reps, const char* path) {
     {
         std::lock_guard<std::mutex> lk(c->plan_mu);
         c->cost = cm;
-        c->plans.clear();
+        c->cost_changed();
     }
     if (path) return save_json(cm, precs, path);
     return PA_OK;
@@ -174,7 +174,7 @@ pa_status tune_load(Ctx* c, const char* path) {
     CostModel cm = c->cost;
     if (load_tune_table(cm, path) <= 0) return PA_EINVAL;
     c->cost = cm;
-    c->plans.clear();
+    c->cost_changed();
     return PA_OK;
 }
 

@@ -181,18 +181,33 @@ def pa_hash_noalloc(ctx, seed, n: int, m: int, key, out, flags: int = 0) -> int:
     return _lib.pa_hash_noalloc(ctx, _ptr(seed), int(n), int(m), _ptr(key), _ptr(out), int(flags) | PA_DEVICE_PTRS)
 
 
+class JobBatch:
+    """The pa_job descriptors of a list of (seed, key, out, n, m), packed once.
+    Repeated pa_hash_batch calls over the same buffers can pass this instead
+    of the list, which skips re-reading 3 addresses per job (about 1 us per
+    job in Python)."""
+
+    def __init__(self, jobs):
+        self.count = len(jobs)
+        self.arr = (pa_job * max(1, self.count))()
+        dev = self.count > 0
+        for i, (seed, key, out, n, m) in enumerate(jobs):
+            self.arr[i] = pa_job(_ptr(seed), _ptr(key), _ptr(out), int(n), int(m))
+            dev = dev and _is_device(seed) and _is_device(key) and _is_device(out)
+        self.device = dev
+        self.jobs = list(jobs)   # keeps the buffers alive with the descriptors
+
+
 def pa_hash_batch(ctx, jobs, flags: int = 0):
-    """jobs: list of (seed, key, out, n, m).  Returns (status, per-job statuses)."""
-    arr = (pa_job * len(jobs))()
-    dev = len(jobs) > 0
-    for i, (seed, key, out, n, m) in enumerate(jobs):
-        arr[i] = pa_job(_ptr(seed), _ptr(key), _ptr(out), int(n), int(m))
-        dev = dev and _is_device(seed) and _is_device(key) and _is_device(out)
-    if dev:
+    """jobs: list of (seed, key, out, n, m), or a JobBatch of such a list.
+    Returns (status, per-job statuses)."""
+    if not isinstance(jobs, JobBatch):
+        jobs = JobBatch(jobs)
+    if jobs.device:
         flags |= PA_DEVICE_PTRS
-    per = (ctypes.c_int * max(1, len(jobs)))()
-    st = _lib.pa_hash_batch(ctx, arr, len(jobs), int(flags), per)
-    return st, [int(per[i]) for i in range(len(jobs))]
+    per = (ctypes.c_int * max(1, jobs.count))()
+    st = _lib.pa_hash_batch(ctx, jobs.arr, jobs.count, int(flags), per)
+    return st, list(per)[:jobs.count]
 
 
 def pa_hash_select(ctx, seed, n: int, m: int, key, idx, flags: int = 0):

@@ -85,6 +85,44 @@ def test_batch_equals_single_calls(pa, ctx, flags):
             assert np.array_equal(yb, oracle.hash_words(p.seed, p.n, p.m, p.key)), (p.n, p.m)
 
 
+def test_batch_plan_reuse(pa, ctx):
+    """A batch of the shapes of an earlier one reuses its plan: repeated calls
+    on a packed JobBatch, the same shapes in another order, and one shape
+    changed all match the oracle (the cache is keyed by every job's n and m,
+    in order)."""
+    import torch
+    rng = np.random.default_rng(14)
+    shapes = [(120_000, 9_000), (3_000, 70), (400_001, 150_000), (90_000, 40_000), (2_000_000, 100_000)]
+    probs = [synth.random_problem(rng, n, m) for n, m in shapes]
+    want = [oracle.hash_words(p.seed, p.n, p.m, p.key) for p in probs]
+    dev = [_dev_job(p) for p in probs]
+    jb = pa.JobBatch(dev)
+    assert jb.device and jb.count == len(dev)
+    for rep in range(3):
+        for d in dev:
+            d[2].zero_()
+        st, per = pa.pa_hash_batch(ctx, jb, pa.PA_PREC_AUTO)
+        torch.cuda.synchronize()
+        assert st == pa.PA_OK and per == [pa.PA_OK] * len(dev), (rep, per)
+        for k, (p, d) in enumerate(zip(probs, dev)):
+            assert np.array_equal(_words(d[2], p.m), want[k]), (rep, k)
+    order = [3, 0, 4, 2, 1]
+    rev = [_dev_job(probs[k]) for k in order]
+    st, per = pa.pa_hash_batch(ctx, rev, pa.PA_PREC_AUTO)
+    torch.cuda.synchronize()
+    assert st == pa.PA_OK
+    for j, k in enumerate(order):
+        assert np.array_equal(_words(rev[j][2], probs[k].m), want[k]), ("reordered", k)
+    other = synth.random_problem(rng, 250_000, 60_000)
+    mixed = [_dev_job(probs[0]), _dev_job(other)] + [_dev_job(p) for p in probs[2:]]
+    st, per = pa.pa_hash_batch(ctx, mixed, pa.PA_PREC_AUTO)
+    torch.cuda.synchronize()
+    assert st == pa.PA_OK
+    assert np.array_equal(_words(mixed[1][2], other.m), oracle.hash_words(other.seed, other.n, other.m, other.key))
+    for j, p in zip([0, 2, 3, 4], [probs[0]] + probs[2:]):
+        assert np.array_equal(_words(mixed[j][2], p.m), oracle.hash_words(p.seed, p.n, p.m, p.key)), j
+
+
 def test_batch_host_pointers(pa, ctx):
     rng = np.random.default_rng(12)
     probs = [synth.random_problem(rng, n, m) for n, m in [(1000, 200), (77, 1000), (300_000, 5000)]]
