@@ -236,25 +236,34 @@ k2_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const
 
 // ------------------------------------------------------------------ pass 2
 // Shared memory of the row pass: the row exchange / wave regions, the stage
-// tables of the 1024-point transforms, and (FP32) the first-stage twiddles
-// t8[(ka-1) 1024 + nb] = w_8192^{ka nb}, ka = 1..7.  FP64 reads those from the
-// global table instead (its row region leaves no room): 156.7 KB vs 135.7 KB.
+// tables of the 1024-point transforms, and the first-stage twiddles
+// w_8192^{ka nb}, ka = 1..7: FP32 holds them all, t8[(ka-1) 1024 + nb]; FP64,
+// whose row region leaves no room for that, forms them as the product of two
+// short tables, w_8192^e = w8a[e >> 6] w8b[e & 63] (135.7 KB for FP32, 156 KB
+// for FP64).
 template <typename T> struct RowSmem {
-    static constexpr bool kLds = sizeof(T) == 4;   // tables in LDS (FP32 only)
+    static constexpr bool kLds = sizeof(T) == 4;   // the full first-stage table (FP32 only)
     cx<T> data[8 * kWaveSlots];
-    cx<T> st[kLds ? wfft_lds_entries(1024) : 1];
+    cx<T> st[wfft_lds_entries(1024)];
     cx<T> t8[kLds ? 7 * 1024 : 1];
+    cx<T> w8a[kLds ? 1 : 128];
+    cx<T> w8b[kLds ? 1 : 64];
 };
 
-// Thread tid writes t8 entries e = tid (mod 512) and the forward transform's
-// thread tid reads only such entries (nb = tid + 512 s), so the first unit
-// needs no barrier after this load; the stage tables are first read after one.
+// FP32: thread tid writes t8 entries e = tid (mod 512) and the forward
+// transform's thread tid reads only such entries (nb = tid + 512 s), so the
+// first unit needs no barrier after this load; the stage tables are first
+// read after one.  FP64 reads w8a / w8b entries other threads wrote: the
+// kernel waits at a barrier after this load.
 template <typename T>
 __device__ __forceinline__ void row_smem_load(RowSmem<T>& S, const cx<T>* __restrict__ tw,
                                               const cx<T>* __restrict__ stw, int tid) {
+    wfft_load_lds<T, 1024>(S.st, stw, tid, 512);
     if constexpr (RowSmem<T>::kLds) {
-        wfft_load_lds<T, 1024>(S.st, stw, tid, 512);
         for (int e = tid; e < 7 * 1024; e += 512) S.t8[e] = tw[(1 + e / 1024) * (e % 1024)];
+    } else {
+        if (tid < 128) S.w8a[tid] = tw[64 * tid];
+        if (tid < 64) S.w8b[tid] = tw[tid];
     }
 }
 
@@ -264,20 +273,25 @@ template <typename T> struct RowReg {
     cx<T> tr[RowSmem<T>::kLds ? 15 : 1];
 };
 
-// 1024-point wave transform of the row pass, stage tables from LDS (and
-// registers) or global
+// 1024-point wave transform of the row pass, stage tables from LDS (FP32:
+// the last stage's from registers)
 template <typename T, int DIR>
 __device__ __forceinline__ void row_wave_fft(cx<T> (&v)[16], cx<T>* __restrict__ reg, int l, const RowSmem<T>& S,
                                              const RowReg<T>& R, const cx<T>* __restrict__ stw) {
+    (void)stw;
     if constexpr (RowSmem<T>::kLds) wave_fft1024_lds_reg<T, DIR>(v, reg, l, S.st, R.tr);
-    else wave_fft<T, DIR, 1024>(v, reg, l, stw);
+    else wave_fft_lds<T, DIR, 1024>(v, reg, l, S.st);
 }
 
 // w_8192^{ka nb}, 1 <= ka < 8, nb < 1024
 template <typename T>
 __device__ __forceinline__ cx<T> w8192(const RowSmem<T>& S, const cx<T>* __restrict__ tw, int ka, int nb) {
-    if constexpr (RowSmem<T>::kLds) return S.t8[(ka - 1) * 1024 + nb];
-    else return opaque(tw)[ka * nb];
+    if constexpr (RowSmem<T>::kLds) {
+        return S.t8[(ka - 1) * 1024 + nb];
+    } else {
+        const int e = ka * nb;   // < 7168
+        return cmul(S.w8a[e >> 6], S.w8b[e & 63]);
+    }
 }
 
 template <typename T>
@@ -402,8 +416,8 @@ __device__ __forceinline__ void row_store(cx<T>* __restrict__ Yrow, cx<T> (&a)[1
 
 // Row pass over units: units 0 .. ntiles (n2/2 - 1) - 1 are mirror pairs (row
 // pr >= 1 with n2 - pr), the last ntiles units the self rows 0 and n2/2 of
-// each tile.  FP32 is persistent (workgroup b walks u = b, b + G, ..., G = one
-// workgroup per CU, tables loaded once); FP64 runs one unit per workgroup.
+// each tile.  The pass is persistent: workgroup b walks u = b, b + G, ...,
+// G = one workgroup per CU (LDS-bound), tables loaded once.
 template <typename T> constexpr bool kRowPersistent = sizeof(T) == 4;
 // One unit of the row pass.
 template <typename T, int N2, int NCB1>
@@ -475,6 +489,7 @@ k2_pass2(JobTable jt, cx<T>* __restrict__ ws, const uint32_t* __restrict__ part,
     __shared__ uint32_t wsum;
     const uint32_t units = jt.ntiles * (uint32_t)(N2 / 2);
     row_smem_load<T>(S, tw, stw, threadIdx.x);
+    if constexpr (!RowSmem<T>::kLds) __syncthreads();
     RowReg<T> R;
     if constexpr (RowSmem<T>::kLds) {
         // w_1024^{l r} = w_8192^{8 l r}, l r < 1024
