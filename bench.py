@@ -502,7 +502,7 @@ def main():
     if not args.no_batch and not args.only:
         jobs = synth.batch_jobs()
         log(f"[bench] c4 batch of {len(jobs)} jobs")
-        bsteps = max(2, args.steps // 4)
+        bsteps = max(10, args.steps)
         # segment sizes from the tuner: a context of its own measures the class
         # costs first (the headline context keeps the built-in model)
         bctx = pa.pa_create(0, 0, None)

@@ -129,7 +129,7 @@ typedef struct {
  * length class (each job's cheapest class, groups folded together while that
  * lowers the summed cost); each group runs as one launch per pipeline pass for
  * all its tiles.  The groups run concurrently on the context's stream and on
- * PA_BATCH_LANES - 1 side streams of the context (default 3 streams in all),
+ * PA_BATCH_LANES - 1 side streams of the context (default 2 streams in all),
  * forked from the context's stream.  Tile and segment sizes come from the cost
  * model (tuned when pa_tune ran).  Jobs that the precision bits put on the
  * direct path (PA_PREC_DIRECT, or PA_PREC_AUTO where it is modeled cheaper)

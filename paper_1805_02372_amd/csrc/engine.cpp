@@ -816,11 +816,11 @@ pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m, con
 }  // extern "C"
 
 namespace pa {
-// Side streams for batches: PA_BATCH_LANES (default 3, 1..8) streams in all,
+// Side streams for batches: PA_BATCH_LANES (default 2, 1..8) streams in all,
 // the context's stream included.  Called with the context mutex held.
 pa_status ensure_side_lanes(Ctx* c) {
     const char* e = getenv("PA_BATCH_LANES");
-    const int want = std::max(1, std::min(e ? atoi(e) : 3, 8)) - 1;
+    const int want = std::max(1, std::min(e ? atoi(e) : 2, 8)) - 1;
     if ((int)c->side.size() >= want) return PA_OK;
     while ((int)c->side.size() < want) {
         c->side.emplace_back();
