@@ -209,12 +209,16 @@ k2_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = cmul(v[i], rounded<T>(mul64(base, cw[i])));
     __syncthreads();
-    // transpose through LDS for row-segment stores
+    // transpose through LDS for row-segment stores.  With W = 2 the rows
+    // k2 = 2 e + ka of each half go to a tile of their own (the second one 8
+    // slots further, off the first's banks), so that a wave writes
+    // consecutive rows e as in the W = 1 layout
+    constexpr int HALF = M * C + 8;
+    static_assert(W * HALF <= SLOTS, "transposition tiles fit the LDS union");
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int e = j + i * NJ;
-        const int k2 = (W == 1) ? e : 2 * e + ka;
-        lds[tslot<C>(k2, f)] = v[i];
+        lds[ka * HALF + tslot<C>(e, f)] = v[i];
     }
     __syncthreads();
     cx<T>* __restrict__ Y = ws + (size_t)lt * L;
@@ -223,8 +227,8 @@ k2_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const
     cx<T> o[SPT];
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
-        const int idx = tid + q * Gm::THREADS;
-        o[q] = lds[tslot<C>(idx / C, idx % C)];
+        const int idx = tid + q * Gm::THREADS, k2 = idx / C;
+        o[q] = lds[(k2 % W) * HALF + tslot<C>(k2 / W, idx % C)];
     }
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
