@@ -41,7 +41,7 @@ def log(*a):
 
 KERNEL_SOURCES = ("conv_fp32.hip", "conv_fp64.hip", "conv_fp32_p3.hip", "conv_fp32_p5.hip", "conv_fp32_p7.hip",
                   "conv_fp64_p3.hip", "conv_fp64_p5.hip", "conv_fp64_p7.hip", "conv_kernels.hpp", "conv_v2.hpp",
-                  "fft_core.hpp", "wave_fft.hpp", "ntt.hip", "pa_internal.hpp")
+                  "fft_core.hpp", "wave_fft.hpp", "ntt.hip", "pa_internal.hpp", "tile_fused.hpp")
 
 
 def kernel_source_digest() -> str:

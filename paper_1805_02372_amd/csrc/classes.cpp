@@ -5,6 +5,7 @@
 #include <atomic>
 
 #include "pa_internal.hpp"
+#include "planner.hpp"
 
 namespace pa {
 
@@ -39,14 +40,24 @@ static const ClassKernels* smooth_kernels(int prec, int cls) {
     return nullptr;
 }
 
-// Kernels of class `cls` (ids in pa_internal.hpp); the mixed-radix classes
-// exist for FP32 and FP64 only.
-const ClassKernels* class_kernels(int prec, int cls) {
+static const ClassKernels* find_kernels(int prec, int cls) {
     const bool smooth = cls >= 32;
     if (prec == 32) return smooth ? smooth_kernels(32, cls) : class_kernels32(cls);
     if (prec == 64) return smooth ? smooth_kernels(64, cls) : class_kernels64(cls);
     if (prec == 1) return smooth ? nullptr : class_kernels_ntt(cls);
     return nullptr;
+}
+
+// Kernels of class `cls` (ids in pa_internal.hpp); the mixed-radix classes
+// exist for FP32 and FP64 only.  A class whose compiled row and column
+// lengths differ from the planner's geometry (from which its root tables are
+// built) is refused rather than run with tables of another shape.
+const ClassKernels* class_kernels(int prec, int cls) {
+    const ClassKernels* k = find_kernels(prec, cls);
+    if (!k) return nullptr;
+    ClassGeom g;   // Prec values are the precision ids used here
+    if (!class_geometry(prec, cls, &g) || g.n1 != k->cfg.n1 || g.n2 != k->cfg.n2) return nullptr;
+    return k;
 }
 
 }  // namespace pa

@@ -1,9 +1,11 @@
-// FFT length classes for FP64 tiles.  2^12 .. 2^19: L = n1 * n2 with
-// n2 = 2^max(logL-13, min(11, logL/2)), workgroup-wide Stockham stages
-// (conv_kernels.hpp).  2^20 .. 2^24: n1 = 8192, n2 = L / 8192, wave-level transforms
-// (conv_v2.hpp).
+// FFT length classes for FP64 tiles.  2^12 .. 2^13: one kernel per tile, the
+// whole length in one workgroup (tile_fused.hpp).  2^14 .. 2^19: L = n1 * n2
+// with n2 = 2^max(logL-13, min(11, logL/2)), workgroup-wide Stockham stages
+// (conv_kernels.hpp).  2^20 .. 2^24: n1 = 8192, n2 = L / 8192, wave-level
+// transforms (conv_v2.hpp).
 #include "conv_kernels.hpp"
 #include "conv_v2.hpp"
+#include "tile_fused.hpp"
 
 namespace pa {
 
@@ -13,10 +15,13 @@ namespace pa {
 #define PA_CLASS2(LOGL, N2) \
     {ClassCfg{64, LOGL, kN1, N2, ClassImpl2<double, N2>::C1, ClassImpl2<double, N2>::C3, 16}, \
      &ClassImpl2<double, N2>::pass1, &ClassImpl2<double, N2>::pass2, &ClassImpl2<double, N2>::pass3}
+#define PA_FUSED(LOGL) \
+    {ClassCfg{64, LOGL, 1 << LOGL, 1, 1 << LOGL, 1 << LOGL, 16}, &ClassImplF<double, 1 << LOGL>::pass1, \
+     &ClassImplF<double, 1 << LOGL>::pass2, &ClassImplF<double, 1 << LOGL>::pass3}
 
 static const ClassKernels kClasses64[] = {
-    PA_CLASS(12, 64, 64),
-    PA_CLASS(13, 128, 64),
+    PA_FUSED(12),
+    PA_FUSED(13),
     PA_CLASS(14, 128, 128),
     PA_CLASS(15, 256, 128),
     PA_CLASS(16, 256, 256),

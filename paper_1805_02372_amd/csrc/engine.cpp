@@ -401,11 +401,12 @@ static pa_status run_passes(const ClassKernels* K, JobTable jt, uint32_t first, 
         const launch_fn fns[3] = {K->pass1, K->pass2, K->pass3};
         for (int p = 0; p < 3; ++p) {
             hipEvent_t a = timing ? ln->timer.mark(ln->stream) : nullptr;
-            if (fns[p](jt, ln->ws.ptr, (uint32_t*)ln->part.ptr, (TileMeta*)ln->meta.ptr, tb, ln->stream))
-                return PA_EDEVICE;
+            // 0: launched; 1: nothing to launch (one-kernel tiles); < 0: error
+            const int r = fns[p](jt, ln->ws.ptr, (uint32_t*)ln->part.ptr, (TileMeta*)ln->meta.ptr, tb, ln->stream);
+            if (r < 0) return PA_EDEVICE;
+            if (r == 0) *launches += 1;
             if (timing) ln->timer.spans.push_back({p, {a, ln->timer.mark(ln->stream)}});
         }
-        *launches += 3;
     }
     return PA_OK;
 }
@@ -472,6 +473,7 @@ pa_status Lane::launch(Ctx* c, int prec_, int cls_, std::vector<JobDesc>& js, bo
             return PA_EDEVICE;
         jt.many = (const JobDesc*)jobs_dev.ptr;
         jt.njobs = (uint32_t)js.size();
+        for (const JobDesc& jd : js) jt.clears |= (jd.nchunks > 1 && !jd.no_clear) ? 1u : 0u;
     }
     if (timing) timer.reset();
     st = run_passes(K, jt, 0, total, G, this, tb, timing, &stats->launches);

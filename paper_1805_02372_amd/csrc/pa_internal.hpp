@@ -37,6 +37,7 @@ struct JobTable {
     uint32_t njobs;       // 0: use `one`
     uint32_t tile0;       // first tile of this launch (groups of tiles)
     uint32_t ntiles;      // tiles in this launch
+    uint32_t clears;      // some job of `many` has a chunk-0 tile that clears its window
 };
 
 // Per-tile results of pass 2/3.
@@ -89,6 +90,9 @@ struct Tables {
     const double* fb64;
 };
 
+// Enqueues one pass of a class on `stream`: 0 when a kernel was launched, 1
+// when the pass has no kernel for this launch (one-kernel tiles), -1 on a
+// launch error.
 typedef int (*launch_fn)(const JobTable& jt, void* ws, uint32_t* part, TileMeta* meta,
                          const Tables& tb, void* stream);
 

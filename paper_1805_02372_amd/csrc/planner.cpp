@@ -68,9 +68,10 @@ bool class_geometry(int prec, int cls, ClassGeom* g) {
         // power-of-two rows: those of the class 2^k below 2^20, else 8192;
         // the columns carry the factor P (radix-P stage, 4P points per thread)
         const int P = smooth_P(cls), k = smooth_k(cls);
-        ClassGeom base;
-        class_geometry(prec, k, &base);
-        g->n1 = L >= (1ull << 20) ? 8192 : base.n1;
+        // rows of the three-pass geometry of 2^k (its short lengths run as
+        // one-kernel tiles, whose row is the whole length)
+        const int n2log = std::max(k - 13, std::min(prec == PREC_FP64 ? 11 : 10, k / 2));
+        g->n1 = L >= (1ull << 20) ? 8192 : 1 << (k - n2log);
         g->n2 = (int)(L / (uint64_t)g->n1);
         g->b1 = prec == PREC_FP64 ? 4 : 8;
         g->b3 = prec == PREC_FP64 ? 8 : 16;
@@ -97,6 +98,13 @@ bool class_geometry(int prec, int cls, ClassGeom* g) {
         g->n2 = n2;
         g->b1 = waves1 * (1024 / m) / w;
         g->b3 = waves3 * g3;
+        return true;
+    }
+    if (logL <= 13) {   // one-kernel tiles: the whole length in one workgroup
+        g->n1 = 1 << logL;
+        g->n2 = 1;
+        g->b1 = g->n1;
+        g->b3 = g->n1;
         return true;
     }
     int n2cap = prec == PREC_FP64 ? 11 : 10;

@@ -123,6 +123,29 @@ def test_batch_plan_reuse(pa, ctx):
         assert np.array_equal(_words(mixed[j][2], p.m), oracle.hash_words(p.seed, p.n, p.m, p.key)), j
 
 
+@pytest.mark.parametrize("cap", [12, 14])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_one_kernel_tiles(pa, ctx, cap, prec, monkeypatch):
+    """Jobs on the one-kernel tiles (up to 2^13) and the three-pass 2^14 tiles in one
+    batch: some accumulate key chunks, so the launch first clears their
+    windows (a kernel of its own) and the tiles of every chunk XOR into them;
+    each job against the oracle."""
+    import torch
+    monkeypatch.setenv("PA_MAX_LOG2_LEN", str(cap))
+    f = pa.PA_PREC_FP32_SEG if prec == "fp32" else pa.PA_PREC_FP64
+    rng = np.random.default_rng(15 + cap)
+    shapes = [(20_000, 900), (5_000, 3_000), (9_000, 20_000), (100, 50), (60_000, 2_000), (1, 1)]
+    probs = [synth.random_problem(rng, n, m) for n, m in shapes]
+    dev = [_dev_job(p) for p in probs]
+    st, per = pa.pa_hash_batch(ctx, dev, f)
+    torch.cuda.synchronize()
+    assert st == pa.PA_OK and per == [pa.PA_OK] * len(dev), (st, per)
+    stats = pa.pa_last_stats(ctx)
+    assert stats["fft_len"] <= 1 << cap
+    for p, d in zip(probs, dev):
+        assert np.array_equal(_words(d[2], p.m), oracle.hash_words(p.seed, p.n, p.m, p.key)), (p.n, p.m)
+
+
 def test_batch_host_pointers(pa, ctx):
     rng = np.random.default_rng(12)
     probs = [synth.random_problem(rng, n, m) for n, m in [(1000, 200), (77, 1000), (300_000, 5000)]]
