@@ -15,6 +15,8 @@
 //    LDS, each wave inverts G columns, output bits are OR-ed into an LDS bit
 //    array and stored as C-bit groups.
 #pragma once
+#include <type_traits>
+
 #include "conv_kernels.hpp"
 #include "wave_fft.hpp"
 
@@ -236,6 +238,123 @@ k2_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const
         Y[(size_t)(idx / C) * kN1 + cb * C + (idx % C)] = o[q];
     }
     if (tid == 0) part[(size_t)lt * NCB + cb] = wsum;
+}
+
+// Pass 1 for FP32 columns of 2048 points: eight waves, one column each (C = 8
+// columns per workgroup), each wave transforming its column's two halves one
+// after the other.  Half ka (outputs k2 = 2 e + ka) is the 1024-point
+// transform of z(e) + z(e + 1024) (ka = 0) or (z(e) - z(e + 1024)) w_2048^e
+// (ka = 1): a radix-2 split in decimation in frequency.  The LDS holds one
+// half at a time (the block's key/seed bits, then the wave regions, then the
+// transposition tile), and the bits are staged again for the second half, so
+// that two workgroups fit a CU (78 KB each; k2_pass1 with 16 waves needs
+// 148 KB for both halves at once).  Each half is a call of its own, so that
+// the register allocation of one half does not carry the other's values.
+struct P1hArgs {
+    JobDesc jd;
+    TileGeo g;
+    uint32_t lt, cb;
+};
+
+template <typename T, int KA>
+__device__ __noinline__ uint32_t pass1_half(const P1hArgs& A, cx<T>* __restrict__ ws, cx<T>* lds, const cx<T>* st,
+                                            const cx<T>* __restrict__ tw, const cx<double>* __restrict__ fa64,
+                                            const cx<double>* __restrict__ fb64, int fshift) {
+    constexpr int N2 = 2048, M = 1024, C = 8, THREADS = 512, NJ = M / 16;
+    constexpr uint32_t L = (uint32_t)kN1 * N2;
+    const int tid = threadIdx.x, wv = tid >> 6, j = tid & 63;
+    const TileGeo& g = A.g;
+    const uint32_t bi = (uint32_t)g.bi, win = (uint32_t)(g.bi + g.bo - 1);
+    const int f = wv;   // this wave's column
+    const uint32_t t1 = A.cb * C + (uint32_t)f;
+    uint16_t* fld = reinterpret_cast<uint16_t*>(lds);   // per row: key bits (low byte), seed bits (high byte)
+    uint32_t pc = 0;
+    __syncthreads();   // the previous half's stores have read the LDS
+    for (int r = tid; r < N2; r += THREADS) {
+        const uint32_t s0 = A.cb * C + (uint32_t)kN1 * (uint32_t)r;
+        const uint32_t kb = (uint32_t)placed_key_bits<C>(A.jd.key, g.j0, bi, L, s0);
+        const uint32_t nv = s0 < win ? ((win - s0) < (uint32_t)C ? (win - s0) : (uint32_t)C) : 0u;
+        const uint32_t sb = (uint32_t)extract_bits(A.jd.seed, g.sigma + s0, nv);
+        fld[r] = (uint16_t)(kb | (sb << 8));
+        pc += (uint32_t)__popc(kb);
+    }
+    __syncthreads();
+    // four-step twiddle w_L^{t1 k2}, k2 = 2 (j + 64 i) + KA: base w_L^{t1 (2 j + KA)}
+    // times c_i = w_L^{128 t1 i} (lane i < 16 fetches c_i; exchanged after the transform)
+    const Root64 base = root64(fa64, fb64, fshift, t1 * (uint32_t)(2 * j + KA));
+    const Root64 cf = root64(fa64, fb64, fshift, j < 16 ? 128u * t1 * (uint32_t)j : 0u);
+    auto z = [&](int r) -> cx<T> {
+        const uint32_t w = fld[r];
+        const T xb = ((w >> f) & 1u) ? T(1) : T(0);
+        const T sv = ((w >> (8 + f)) & 1u) ? T(1) : T(-1);
+        return cx<T>{xb, (t1 + (uint32_t)kN1 * (uint32_t)r < win) ? sv : T(0)};
+    };
+    cx<T> v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int e = j + i * NJ;
+        const cx<T> a = z(e), b = z(e + M);
+        if constexpr (KA == 0) v[i] = a + b;
+        else v[i] = cmul(a - b, tw[e * (kN1 / N2)]);
+    }
+    __syncthreads();   // bits consumed; LDS becomes wave regions
+    cx<T>* reg = lds + wv * kWaveSlots;
+    wave_fft_lds<T, -1, M>(v, reg, j, st);
+    Root64* cw = reinterpret_cast<Root64*>(reg);
+    wave_sync();
+    if (j < 16) cw[j] = cf;
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = cmul(v[i], rounded<T>(mul64(base, cw[i])));
+    __syncthreads();
+    // transpose through LDS for row-segment stores (rows k2 = 2 e + KA)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) lds[tslot<C>(j + i * NJ, f)] = v[i];
+    __syncthreads();
+    cx<T>* __restrict__ Y = ws + (size_t)A.lt * L;
+    constexpr int SPT = M * C / THREADS;
+    cx<T> o[SPT];
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+        const int idx = tid + q * THREADS;
+        o[q] = lds[tslot<C>(idx / C, idx % C)];
+    }
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+        const int idx = tid + q * THREADS;
+        Y[(size_t)(2 * (idx / C) + KA) * kN1 + A.cb * C + (idx % C)] = o[q];
+    }
+    return pc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+k2_pass1h(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const cx<T>* __restrict__ tw,
+          const cx<T>* __restrict__ stw, const cx<double>* __restrict__ fa64, const cx<double>* __restrict__ fb64,
+          int fshift) {
+    constexpr int M = 1024, C = 8, THREADS = 512;
+    constexpr int NCB = kN1 / C;
+    constexpr int SLOTS = 8 * kWaveSlots;
+    static_assert(M * C <= SLOTS && 2048 * (int)sizeof(uint16_t) <= SLOTS * (int)sizeof(cx<T>), "LDS union");
+    __shared__ __align__(16) cx<T> lds[SLOTS];
+    __shared__ __align__(16) cx<T> st[wfft_lds_entries(M)];
+    __shared__ uint32_t wsum;
+    const uint32_t blk = xcd_block();
+    P1hArgs A;
+    A.lt = blk / NCB;
+    A.cb = blk % NCB;
+    const uint32_t t = jt.tile0 + A.lt;
+    A.jd = find_job(jt, t);
+    A.g = tile_geo(A.jd, t - A.jd.tile_begin);
+    const int tid = threadIdx.x;
+    if (tid == 0) wsum = 0;
+    clear_window(A.g, A.cb, NCB, tid, THREADS);
+    wfft_load_lds<T, M>(st, stw, tid, THREADS);
+    const uint32_t pc = pass1_half<T, 0>(A, ws, lds, st, tw, fa64, fb64, fshift);
+    (void)pass1_half<T, 1>(A, ws, lds, st, tw, fa64, fb64, fshift);
+    atomicAdd(&wsum, pc);
+    __syncthreads();
+    if (tid == 0) part[(size_t)A.lt * NCB + A.cb] = wsum;
 }
 
 // ------------------------------------------------------------------ pass 2
@@ -662,9 +781,16 @@ struct ClassImpl2 {
     static constexpr int C1 = G1::C, C3 = G3::C;
     static int pass1(const JobTable& jt, void* ws, uint32_t* part, TileMeta*, const Tables& tb, void* stream) {
         dim3 grid(jt.ntiles * (kN1 / C1)), block(G1::THREADS);
-        hipLaunchKernelGGL((k2_pass1<T, N2>), grid, block, 0, (hipStream_t)stream, jt, (cx<T>*)ws, part,
-                           (const cx<T>*)tb.tw, (const cx<T>*)tb.stw, (const cx<double>*)tb.fa64,
-                           (const cx<double>*)tb.fb64, tb.fshift);
+        if constexpr (sizeof(T) == 4 && N2 == 2048) {
+            static_assert(C1 == 8, "eight columns per workgroup");
+            hipLaunchKernelGGL((k2_pass1h<T>), grid, dim3(512), 0, (hipStream_t)stream, jt, (cx<T>*)ws, part,
+                               (const cx<T>*)tb.tw, (const cx<T>*)tb.stw, (const cx<double>*)tb.fa64,
+                               (const cx<double>*)tb.fb64, tb.fshift);
+        } else {
+            hipLaunchKernelGGL((k2_pass1<T, N2>), grid, block, 0, (hipStream_t)stream, jt, (cx<T>*)ws, part,
+                               (const cx<T>*)tb.tw, (const cx<T>*)tb.stw, (const cx<double>*)tb.fa64,
+                               (const cx<double>*)tb.fb64, tb.fshift);
+        }
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
     static int pass2(const JobTable& jt, void* ws, uint32_t* part, TileMeta* meta, const Tables& tb, void* stream) {
