@@ -166,31 +166,45 @@ typedef struct pa_stream pa_stream;
 /* Open a stream for an (n, m) job.  flags: the precision bits used for every
  * block (as for pa_hash) and PA_DEVICE_PTRS when the pointers given to
  * pa_stream_feed / _state / _resume / _close are device pointers.  The
- * accumulator starts at zero.  The stream uses the context (its stream and
- * budget) and must be closed before the context is destroyed.  PA_EINVAL for
+ * accumulator starts at zero.  The stream has a GPU stream and workspace of
+ * its own (charged to the context's budget), so it may run beside other calls
+ * on the context; calls on one stream must not overlap.  It must be closed
+ * before the context is destroyed.  PA_EINVAL for
  * n == 0, m == 0 or NULL; PA_ENOMEM when the accumulator does not fit the
  * context's budget. */
 pa_status pa_stream_open(pa_ctx* ctx, uint64_t n, uint64_t m, uint32_t flags, pa_stream** stream);
 
 /* XOR the partial hash of key bits [lo, lo+len) into the accumulator.
  * key_block: len bits, bit 0 = key bit lo.  seed_block: len+m-1 bits, bit 0 =
- * seed bit n-lo-len.  Synchronous (the inputs may be reused on return).
- * PA_EINVAL for len == 0, lo+len > n or NULL pointers; errors of pa_hash
- * otherwise (the accumulator is then unchanged). */
+ * seed bit n-lo-len.  The inputs may be reused on return.  Host blocks are
+ * pipelined: the call copies its block to the device and returns while the
+ * block's kernels may still run; the block's certificate is read (FP64
+ * fallback as in pa_hash) by the next call on the stream (feed, state or
+ * close).  A block that fails there (PA_EPRECISION, PA_EDEVICE) is dropped:
+ * that call returns its error and does nothing else (a feed's own block is
+ * not fed), and the accumulator and fed count stay without it, so the caller
+ * can read the state and feed the blocks again.  Device-pointer blocks are
+ * hashed and checked before the call returns.  PA_EINVAL for len == 0,
+ * lo+len > n or NULL pointers; errors of pa_hash otherwise (the block is then
+ * not fed). */
 pa_status pa_stream_feed(pa_stream* stream, const uint64_t* key_block, uint64_t lo, uint64_t len,
                          const uint64_t* seed_block);
 
 /* Copy the accumulator (ceil(m/64) words) to acc and the number of key bits
- * fed so far to *fed_bits (either may be NULL).  Synchronous. */
+ * fed so far to *fed_bits (either may be NULL), after the block in flight.
+ * Synchronous.  The error of a block in flight that fails (see
+ * pa_stream_feed) is returned instead, with nothing written. */
 pa_status pa_stream_state(pa_stream* stream, uint64_t* acc, uint64_t* fed_bits);
 
 /* Replace the accumulator by acc (ceil(m/64) words, e.g. a saved state) and
- * the fed-bit count by fed_bits.  PA_EINVAL for fed_bits > n or NULL acc. */
+ * the fed-bit count by fed_bits; a block in flight is completed and replaced
+ * with the rest.  PA_EINVAL for fed_bits > n or NULL acc. */
 pa_status pa_stream_resume(pa_stream* stream, const uint64_t* acc, uint64_t fed_bits);
 
 /* Write the hash (m bits) to out unless out is NULL, and free the stream.
  * With out != NULL, PA_EINVAL (and nothing written) unless exactly n key bits
- * were fed.  The stream is freed in every case. */
+ * were fed; the error of a failing block in flight is returned likewise.  The
+ * stream is freed in every case. */
 pa_status pa_stream_close(pa_stream* stream, uint64_t* out);
 
 /* ---- serving (continuous batching) ---------------------------------------

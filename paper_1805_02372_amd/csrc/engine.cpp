@@ -736,6 +736,11 @@ void pa_destroy(pa_ctx* ctx) {
     c->main.release(c);
     for (Lane& ln : c->side) ln.release(c);
     c->serving_release();
+    for (StreamRes* r : c->idle_streams) {
+        r->release(c);
+        delete r;
+    }
+    c->idle_streams.clear();
     for (auto& kv : c->tabs) kv.second.buf.release(c);
     c->copier.shutdown();
     delete c;

@@ -120,6 +120,18 @@ struct Lane {
                      bool timing, pa_stats* stats);
 };
 
+// GPU resources of a block stream (pa_stream_*): its lane, a copy stream and
+// two staging slots (device buffer, pinned host image, events).  A closed
+// stream's resources stay with the context for the next stream.
+struct StreamRes {
+    Lane ln;
+    hipStream_t copy = nullptr;
+    DevBuf part, in[2];
+    HostBuf pin[2];
+    hipEvent_t staged[2] = {}, used[2] = {};
+    void release(Ctx* c);
+};
+
 // One serving request.
 struct Request {
     uint64_t ticket = 0;
@@ -160,6 +172,8 @@ struct Ctx {
         plans.clear();
         batch_plans.clear();
     }
+    std::mutex stream_mu;
+    std::vector<StreamRes*> idle_streams;   // resources of closed block streams
     bool pools = false;   // stream-ordered allocation supported on the device
     pa_stats last{};
     CopyPool copier;

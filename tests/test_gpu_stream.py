@@ -119,3 +119,79 @@ def test_stream_errors(pa, ctx):
     assert pa.pa_stream_close(s, out) == pa.PA_EINVAL                    # only 100 of 1000 bits fed
     st, _ = pa.pa_stream_open(ctx, 0, m, 0)
     assert st == pa.PA_EINVAL
+
+
+def test_stream_many_blocks_both_slots(pa, ctx):
+    """Sixteen host blocks of mixed lengths (direct-product and FFT blocks
+    alternate, staging buffers grow) in a shuffled order."""
+    rng = np.random.default_rng(66)
+    n, m = 4_000_000, 70_000
+    p = synth.random_problem(rng, n, m)
+    cuts = sorted(set(int(c) for c in rng.integers(1, n, 15)))
+    blocks = _blocks(n, cuts)
+    order = rng.permutation(len(blocks))
+    st, s = pa.pa_stream_open(ctx, n, m, pa.PA_PREC_AUTO)
+    assert st == pa.PA_OK
+    fed = 0
+    for k in order:
+        lo, length = blocks[k]
+        print(f"feed block lo={lo} len={length}", flush=True)
+        assert _feed(pa, s, p, lo, length) == pa.PA_OK
+        fed += length
+    st, got = pa.pa_stream_state(s)
+    assert st == pa.PA_OK and got == fed == n
+    out = np.zeros(synth.words_for(m), np.uint64)
+    assert pa.pa_stream_close(s, out) == pa.PA_OK
+    assert np.array_equal(out, oracle.hash_words(p.seed, n, m, p.key))
+
+
+def test_stream_resume_replaces_block_in_flight(pa, ctx):
+    """A resume issued while a host block may still run replaces it."""
+    rng = np.random.default_rng(67)
+    n, m = 2_000_000, 50_000
+    p = synth.random_problem(rng, n, m)
+    blocks = _blocks(n, [800_000])
+    st, s = pa.pa_stream_open(ctx, n, m, 0)
+    assert st == pa.PA_OK
+    assert _feed(pa, s, p, *blocks[0]) == pa.PA_OK
+    assert pa.pa_stream_resume(s, np.zeros(synth.words_for(m), np.uint64), 0) == pa.PA_OK
+    st, fed = pa.pa_stream_state(s)
+    assert st == pa.PA_OK and fed == 0
+    for lo, length in blocks:
+        assert _feed(pa, s, p, lo, length) == pa.PA_OK
+    out = np.zeros(synth.words_for(m), np.uint64)
+    assert pa.pa_stream_close(s, out) == pa.PA_OK
+    assert np.array_equal(out, oracle.hash_words(p.seed, n, m, p.key))
+
+
+def test_stream_block_error_reported_by_next_call(pa, ctx, monkeypatch):
+    """An all-ones seed with FP32 chunks of more than 2^21 bits fails every
+    tile's certificate (each window value is the chunk's weight).  Without
+    fallback the host block's failure is returned by the next feed, which
+    then feeds nothing: the fed count and accumulator stay empty.  With
+    fallback the same blocks give the closed form: every output is the
+    parity of the key's weight."""
+    from types import SimpleNamespace
+    monkeypatch.setenv("PA_MIN_LOG2_LEN", "22")
+    rng = np.random.default_rng(68)
+    n, m = 6_000_000, 100_000
+    p = SimpleNamespace(n=n, m=m, seed=synth.pattern_bits("ones", n + m - 1), key=synth.gen_bits(rng, n))
+    par = int(np.unpackbits(p.key.view(np.uint8)).sum()) & 1
+    blocks = _blocks(n, [3_000_000])
+    f = pa.PA_PREC_FP32_SEG
+    st, s = pa.pa_stream_open(ctx, n, m, f | pa.PA_NO_FALLBACK)
+    assert st == pa.PA_OK
+    assert _feed(pa, s, p, *blocks[0]) == pa.PA_OK
+    assert _feed(pa, s, p, *blocks[1]) == pa.PA_EPRECISION   # the first block's certificate
+    acc = np.ones(synth.words_for(m), np.uint64)
+    st, fed = pa.pa_stream_state(s, acc)
+    assert st == pa.PA_OK and fed == 0 and not acc.any()
+    assert _feed(pa, s, p, *blocks[1]) == pa.PA_OK
+    assert pa.pa_stream_close(s, None) == pa.PA_EPRECISION   # the second block's, at close
+    st, s = pa.pa_stream_open(ctx, n, m, f)
+    assert st == pa.PA_OK
+    for lo, length in blocks:
+        assert _feed(pa, s, p, lo, length) == pa.PA_OK
+    out = np.zeros(synth.words_for(m), np.uint64)
+    assert pa.pa_stream_close(s, out) == pa.PA_OK
+    assert np.array_equal(synth.bits_to_array(out, m), np.full(m, par, np.uint8))
