@@ -94,7 +94,7 @@ pa_status pa_hash(pa_ctx* ctx, const uint64_t* seed, uint64_t n, uint64_t m,
  * operation, kernels and results as pa_hash with PA_DEVICE_PTRS; the call
  * itself makes no hipMalloc, hipFree or other device or pinned allocation.
  * The workspace, per-tile sums, certificates and twiddle tables live in one
- * fixed array in device memory, about 133 MiB, that every GPU the library runs
+ * fixed array in device memory, about 137 MiB, that every GPU the library runs
  * on holds until the process ends (its address is taken once per device when
  * a context is created there).
  * - seed, key, out: device pointers; flags must include PA_DEVICE_PTRS

@@ -13,7 +13,8 @@ namespace pa {
     {ClassCfg{32, LOGL, N1, N2, 8, 16, 16}, &ClassImpl<float, N1, N2, 8, 16, 16, 16>::pass1, \
      &ClassImpl<float, N1, N2, 8, 16, 16, 16>::pass2, &ClassImpl<float, N1, N2, 8, 16, 16, 16>::pass3}
 #define PA_CLASS2(LOGL, N2) \
-    {ClassCfg{32, LOGL, kN1, N2, ClassImpl2<float, N2>::C1, ClassImpl2<float, N2>::C3, 16}, \
+    {ClassCfg{32, LOGL, kN1, N2, ClassImpl2<float, N2>::C1, ClassImpl2<float, N2>::C3, 16,        \
+              ClassImpl2<float, N2>::kWsExtra},                                                      \
      &ClassImpl2<float, N2>::pass1, &ClassImpl2<float, N2>::pass2, &ClassImpl2<float, N2>::pass3}
 #define PA_FUSED(LOGL) \
     {ClassCfg{32, LOGL, 1 << LOGL, 1, 1 << LOGL, 1 << LOGL, 16}, &ClassImplF<float, 1 << LOGL>::pass1, \

@@ -32,6 +32,7 @@ template <typename T, int N2> struct P1Geom {
     static constexpr int C = WAVES * G / W;                // columns per workgroup
     static constexpr int THREADS = WAVES * 64;
     static_assert(W <= 2, "column length up to 2048");
+    static constexpr bool kPlanes = sizeof(T) == 4 && C == 8;   // bits from the planes of k2_bits
     static_assert(C <= 64 && (C & (C - 1)) == 0, "column block");
 };
 
@@ -84,6 +85,156 @@ __device__ __forceinline__ uint32_t xcd_block() {
 }
 
 // ------------------------------------------------------------------ pass 1
+// Bit planes.  A pass-1 workgroup of 8 columns needs one byte of key bits and
+// one of seed bits from every row of the tile, rows 1 KB apart: read in place,
+// each byte costs a cache line on its way to the compute unit, and staging
+// them took a fifth of pass 1.  For the FP32 classes with 8 columns per
+// workgroup a small kernel first transposes them, coalesced, into two planes
+// per tile after the launch's tiles in the workspace: byte cb n2 + r of the
+// key plane holds the placed key bits at positions 8 cb + 8192 r .. + 7 (bit
+// q: position + q), the seed plane the seed bits there (zero from the window
+// end on).  Pass 1 then reads n2 contiguous bytes of each.
+template <int N2> struct BitPlanes {
+    static constexpr size_t kPlane = (size_t)N2 * (kN1 / 8);
+    static constexpr size_t kTile = 2 * kPlane;   // key plane, then seed plane
+    template <typename T>
+    __device__ static const uint8_t* key(const cx<T>* ws, uint32_t ntiles, uint32_t lt) {
+        return reinterpret_cast<const uint8_t*>(ws + (size_t)ntiles * ((size_t)kN1 * N2)) + (size_t)lt * kTile;
+    }
+};
+
+// 8 x 8 byte transpose: byte c of x[q] moves to byte q of x[c].
+__device__ __forceinline__ void transpose8x8(uint64_t (&x)[8]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint64_t a = x[q], b = x[q + 4];
+        x[q] = (a & 0xFFFFFFFFull) | (b << 32);
+        x[q + 4] = (a >> 32) | (b & 0xFFFFFFFF00000000ull);
+    }
+    constexpr uint64_t m16 = 0x0000FFFF0000FFFFull, m8 = 0x00FF00FF00FF00FFull;
+#pragma unroll
+    for (int q = 0; q < 8; q += (q & 1) ? 3 : 1) {   // q = 0, 1, 4, 5
+        const uint64_t a = x[q], b = x[q + 2];
+        x[q] = (a & m16) | ((b & m16) << 16);
+        x[q + 2] = ((a >> 16) & m16) | (b & ~m16);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; q += 2) {
+        const uint64_t a = x[q], b = x[q + 1];
+        x[q] = (a & m8) | ((b & m8) << 8);
+        x[q + 1] = ((a >> 8) & m8) | (b & ~m8);
+    }
+}
+
+// 64-bit extractions for k2_bits, split into the word loads and the shifts,
+// so that a thread issues all its loads back to back: both words of every
+// extraction are loaded (indices clamped to the array of nw words) and both
+// are used whatever the shift, so no load sits behind a branch.  Same results
+// as extract_bits / placed_key_bits<64>.
+struct Ext64 {
+    uint64_t w;     // first word
+    uint32_t s;     // bit offset in it
+    uint64_t mask;  // cnt low bits
+};
+__device__ __forceinline__ Ext64 ext64(uint64_t pos, uint32_t cnt) {
+    return Ext64{pos >> 6, (uint32_t)(pos & 63), cnt >= 64 ? ~0ull : ((1ull << (cnt & 63)) - 1ull)};
+}
+__device__ __forceinline__ void ext64_load(const uint64_t* __restrict__ a, uint64_t nw, const Ext64& e,
+                                           uint64_t& lo, uint64_t& hi) {
+    lo = a[e.w < nw ? e.w : nw - 1];
+    hi = a[e.w + 1 < nw ? e.w + 1 : nw - 1];
+}
+__device__ __forceinline__ uint64_t ext64_value(const Ext64& e, uint64_t lo, uint64_t hi) {
+    return ((lo >> e.s) | ((hi << 1) << (63 - e.s))) & e.mask;   // s = 0: hi drops out
+}
+// The two extractions of the placed key bits at positions s0 .. s0 + 63
+// (position t holds key bit j0 + ((t + bi - 1) mod L) when that index is < bi):
+// the positions before the wrap to u = 0, then those after it, shifted by fs.
+struct PlacedKey64 {
+    Ext64 e1, e2;
+    uint32_t fs;
+};
+__device__ __forceinline__ PlacedKey64 placed_key64(uint64_t j0, uint32_t bi, uint32_t L, uint32_t s0) {
+    uint32_t u0 = s0 + bi - 1;
+    if (u0 >= L) u0 -= L;
+    const uint32_t fs = u0 + 64 <= L ? 64u : L - u0;
+    const uint32_t c1 = u0 < bi ? (bi - u0 < fs ? bi - u0 : fs) : 0u;
+    const uint32_t c2 = fs < 64 ? (bi < 64 - fs ? bi : 64 - fs) : 0u;
+    return PlacedKey64{ext64(j0 + u0, c1), ext64(j0, c2), fs & 63u};   // c2 = 0 when fs = 64
+}
+
+// Workgroup: 128 rows x 8 word columns (64 positions each) of one tile, both
+// planes, 256 threads.  Loads: 8 consecutive lanes take 8 consecutive words
+// of one row (64 contiguous bytes of key or seed), 4 rows per lane, every
+// load of a lane issued before the first wait.  The words go to LDS; then
+// each lane of one half of the workgroup (key plane, seed plane) reads the
+// word column of 8 consecutive rows, transposes the 8 x 8 bytes and stores
+// one 64-bit word (8 rows) per byte column, so that 16 consecutive lanes write
+// one whole 128-byte line.
+constexpr int kBitsRows = 128, kBitsCols = 8;
+// LDS slot of (row r, word w): bits 3..4 of r permute the rows within each
+// 256-byte bank span and bits 3..5 of r are XOR-ed into the word, so that both
+// the row-wise writes and the column-wise reads of 64 lanes touch every bank
+// pair at most twice.
+__device__ __forceinline__ int bits_slot(int r, int w) {
+    return (r ^ ((r >> 3) & 3)) * kBitsCols + (w ^ ((r >> 3) & 7));
+}
+template <int N2>
+__global__ void __launch_bounds__(256) k2_bits(JobTable jt, uint8_t* __restrict__ planes) {
+    constexpr int R = kBitsRows, WC = kBitsCols, RPL = R * WC / 256;   // rows per lane
+    constexpr int NRB = N2 / R, NWB = kN1 / 64 / WC;
+    constexpr uint32_t L = (uint32_t)kN1 * N2;
+    static_assert(N2 % R == 0 && (kN1 / 64) % WC == 0 && RPL == 4 && WC * 16 * 2 == 256, "workgroup block");
+    __shared__ uint64_t wbits[2][R * WC];   // key words, seed words
+    const uint32_t b = blockIdx.x;
+    const uint32_t lt = b / (NRB * NWB), rem = b % (NRB * NWB);
+    const uint32_t rb = rem / NWB, wb = rem % NWB;
+    const uint32_t t = jt.tile0 + lt;
+    const JobDesc jd = find_job(jt, t);
+    const TileGeo g = tile_geo(jd, t - jd.tile_begin);
+    const uint32_t bi = (uint32_t)g.bi, win = (uint32_t)(g.bi + g.bo - 1);
+    const uint64_t nkw = (jd.n + 63) >> 6, nsw = (jd.n + jd.m - 1 + 63) >> 6;   // key and seed words
+    const int tid = threadIdx.x;
+    {
+        const int wl = tid & (WC - 1);
+        const uint32_t wc = wb * WC + (uint32_t)wl;
+        PlacedKey64 pk[RPL];
+        Ext64 se[RPL];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const int rl = tid / WC + (256 / WC) * q;
+            const uint32_t s0 = wc * 64 + (uint32_t)kN1 * (rb * R + (uint32_t)rl);
+            pk[q] = placed_key64(g.j0, bi, L, s0);
+            const uint32_t nv = s0 < win ? ((win - s0) < 64u ? (win - s0) : 64u) : 0u;
+            se[q] = ext64(g.sigma + s0, nv);
+        }
+        uint64_t kw[RPL][4], sw[RPL][2];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            ext64_load(jd.key, nkw, pk[q].e1, kw[q][0], kw[q][1]);
+            ext64_load(jd.key, nkw, pk[q].e2, kw[q][2], kw[q][3]);
+            ext64_load(jd.seed, nsw, se[q], sw[q][0], sw[q][1]);
+        }
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const int sl = bits_slot(tid / WC + (256 / WC) * q, wl);
+            wbits[0][sl] = ext64_value(pk[q].e1, kw[q][0], kw[q][1]) |
+                           (ext64_value(pk[q].e2, kw[q][2], kw[q][3]) << pk[q].fs);
+            wbits[1][sl] = ext64_value(se[q], sw[q][0], sw[q][1]);
+        }
+    }
+    __syncthreads();
+    const int pl = tid >> 7, p = tid & 15, wl = (tid >> 4) & (WC - 1);   // plane, rows 8 p .. 8 p + 7, word
+    uint64_t x[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = wbits[pl][bits_slot(8 * p + i, wl)];
+    transpose8x8(x);
+    uint8_t* dst = planes + (size_t)lt * BitPlanes<N2>::kTile + (size_t)pl * BitPlanes<N2>::kPlane +
+                   (size_t)((wb * WC + (uint32_t)wl) * 8) * N2 + rb * R + 8 * p;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) *reinterpret_cast<uint64_t*>(dst + (size_t)c * N2) = x[c];
+}
+
 template <typename T, int N2>
 __global__ void __launch_bounds__((P1Geom<T, N2>::THREADS))
 k2_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const cx<T>* __restrict__ tw,
@@ -119,16 +270,24 @@ k2_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const
     constexpr int RPT = (N2 + Gm::THREADS - 1) / Gm::THREADS;
     uint32_t pc = 0;
     uint64_t kb[RPT], sb[RPT];
+    constexpr bool kPlanes = Gm::kPlanes;
+    const uint8_t* kp = nullptr;
+    if constexpr (kPlanes) kp = BitPlanes<N2>::key(ws, jt.ntiles, lt) + (size_t)cb * N2;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int r = tid + q * Gm::THREADS;
         kb[q] = 0;
         sb[q] = 0;
         if (r < N2) {
-            const uint32_t s0 = cb * C + (uint32_t)kN1 * (uint32_t)r;
-            kb[q] = placed_key_bits<C>(jd.key, g.j0, bi, L, s0);
-            const uint32_t nv = s0 < win ? ((win - s0) < (uint32_t)C ? (win - s0) : (uint32_t)C) : 0u;
-            sb[q] = extract_bits(jd.seed, g.sigma + s0, nv);
+            if constexpr (kPlanes) {
+                kb[q] = kp[r];
+                sb[q] = kp[BitPlanes<N2>::kPlane + r];
+            } else {
+                const uint32_t s0 = cb * C + (uint32_t)kN1 * (uint32_t)r;
+                kb[q] = placed_key_bits<C>(jd.key, g.j0, bi, L, s0);
+                const uint32_t nv = s0 < win ? ((win - s0) < (uint32_t)C ? (win - s0) : (uint32_t)C) : 0u;
+                sb[q] = extract_bits(jd.seed, g.sigma + s0, nv);
+            }
         }
     }
 #pragma unroll
@@ -240,26 +399,25 @@ k2_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const
     if (tid == 0) part[(size_t)lt * NCB + cb] = wsum;
 }
 
-// Pass 1 for FP32 columns of 2048 points: eight waves, one column each (C = 8
-// columns per workgroup), each wave transforming its column's two halves one
-// after the other.  Half ka (outputs k2 = 2 e + ka) is the 1024-point
-// transform of z(e) + z(e + 1024) (ka = 0) or (z(e) - z(e + 1024)) w_2048^e
-// (ka = 1): a radix-2 split in decimation in frequency.  The LDS holds one
-// half at a time (the block's key/seed bits, then the wave regions, then the
-// transposition tile), and the bits are staged again for the second half, so
-// that two workgroups fit a CU (78 KB each; k2_pass1 with 16 waves needs
-// 148 KB for both halves at once).  Each half is a call of its own, so that
-// the register allocation of one half does not carry the other's values.
+// Pass 1 for FP32 columns of 2048 points, as two halves.  Half ka (outputs
+// k2 = 2 e + ka) is the 1024-point transform of z(e) + z(e + 1024) (ka = 0) or
+// (z(e) - z(e + 1024)) w_2048^e (ka = 1): a radix-2 split in decimation in
+// frequency.  A workgroup of eight waves takes one half of 8 columns (one
+// column per wave), so it needs the LDS of one half (the block's bits, then
+// the wave regions, then the transposition tile: 78 KB, two workgroups per
+// CU) and the registers of one 1024-point column; the two halves of a column
+// block read the same bit-plane bytes.
 struct P1hArgs {
     JobDesc jd;
     TileGeo g;
-    uint32_t lt, cb;
+    uint32_t lt, cb, ntiles;
 };
 
 template <typename T, int KA>
-__device__ __noinline__ uint32_t pass1_half(const P1hArgs& A, cx<T>* __restrict__ ws, cx<T>* lds, const cx<T>* st,
-                                            const cx<T>* __restrict__ tw, const cx<double>* __restrict__ fa64,
-                                            const cx<double>* __restrict__ fb64, int fshift) {
+__device__ __forceinline__ uint32_t pass1_half_body(const P1hArgs& A, cx<T>* __restrict__ ws, cx<T>* lds,
+                                                    const cx<T>* st, const cx<T>* __restrict__ tw,
+                                                    const cx<double>* __restrict__ fa64,
+                                                    const cx<double>* __restrict__ fb64, int fshift) {
     constexpr int N2 = 2048, M = 1024, C = 8, THREADS = 512, NJ = M / 16;
     constexpr uint32_t L = (uint32_t)kN1 * N2;
     const int tid = threadIdx.x, wv = tid >> 6, j = tid & 63;
@@ -270,11 +428,10 @@ __device__ __noinline__ uint32_t pass1_half(const P1hArgs& A, cx<T>* __restrict_
     uint16_t* fld = reinterpret_cast<uint16_t*>(lds);   // per row: key bits (low byte), seed bits (high byte)
     uint32_t pc = 0;
     __syncthreads();   // the previous half's stores have read the LDS
+    const uint8_t* kp = BitPlanes<N2>::key(ws, A.ntiles, A.lt) + (size_t)A.cb * N2;
     for (int r = tid; r < N2; r += THREADS) {
-        const uint32_t s0 = A.cb * C + (uint32_t)kN1 * (uint32_t)r;
-        const uint32_t kb = (uint32_t)placed_key_bits<C>(A.jd.key, g.j0, bi, L, s0);
-        const uint32_t nv = s0 < win ? ((win - s0) < (uint32_t)C ? (win - s0) : (uint32_t)C) : 0u;
-        const uint32_t sb = (uint32_t)extract_bits(A.jd.seed, g.sigma + s0, nv);
+        const uint32_t kb = kp[r];
+        const uint32_t sb = kp[BitPlanes<N2>::kPlane + r];
         fld[r] = (uint16_t)(kb | (sb << 8));
         pc += (uint32_t)__popc(kb);
     }
@@ -327,9 +484,12 @@ __device__ __noinline__ uint32_t pass1_half(const P1hArgs& A, cx<T>* __restrict_
     return pc;
 }
 
+// Each half in a workgroup of its own: logical block 2 b + KA
+// takes half KA of column block b (the two read the same bit words, through
+// the L2 of one XCD).  Half 0 clears the window and reports the weight.
 template <typename T>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
-k2_pass1h(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const cx<T>* __restrict__ tw,
+k2_pass1s(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, const cx<T>* __restrict__ tw,
           const cx<T>* __restrict__ stw, const cx<double>* __restrict__ fa64, const cx<double>* __restrict__ fb64,
           int fshift) {
     constexpr int M = 1024, C = 8, THREADS = 512;
@@ -340,18 +500,24 @@ k2_pass1h(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part, cons
     __shared__ __align__(16) cx<T> st[wfft_lds_entries(M)];
     __shared__ uint32_t wsum;
     const uint32_t blk = xcd_block();
+    const uint32_t lb = blk >> 1;
+    const bool second = (blk & 1u) != 0;
     P1hArgs A;
-    A.lt = blk / NCB;
-    A.cb = blk % NCB;
+    A.lt = lb / NCB;
+    A.cb = lb % NCB;
+    A.ntiles = jt.ntiles;
     const uint32_t t = jt.tile0 + A.lt;
     A.jd = find_job(jt, t);
     A.g = tile_geo(A.jd, t - A.jd.tile_begin);
     const int tid = threadIdx.x;
     if (tid == 0) wsum = 0;
-    clear_window(A.g, A.cb, NCB, tid, THREADS);
+    if (!second) clear_window(A.g, A.cb, NCB, tid, THREADS);
     wfft_load_lds<T, M>(st, stw, tid, THREADS);
-    const uint32_t pc = pass1_half<T, 0>(A, ws, lds, st, tw, fa64, fb64, fshift);
-    (void)pass1_half<T, 1>(A, ws, lds, st, tw, fa64, fb64, fshift);
+    if (second) {
+        (void)pass1_half_body<T, 1>(A, ws, lds, st, tw, fa64, fb64, fshift);
+        return;
+    }
+    const uint32_t pc = pass1_half_body<T, 0>(A, ws, lds, st, tw, fa64, fb64, fshift);
     atomicAdd(&wsum, pc);
     __syncthreads();
     if (tid == 0) part[(size_t)A.lt * NCB + A.cb] = wsum;
@@ -779,11 +945,18 @@ struct ClassImpl2 {
     using G1 = P1Geom<T, N2>;
     using G3 = P3Geom<T, N2>;
     static constexpr int C1 = G1::C, C3 = G3::C;
+    // workspace bytes per tile beyond its points: the bit planes
+    static constexpr size_t kWsExtra = G1::kPlanes ? BitPlanes<N2>::kTile : 0;
     static int pass1(const JobTable& jt, void* ws, uint32_t* part, TileMeta*, const Tables& tb, void* stream) {
         dim3 grid(jt.ntiles * (kN1 / C1)), block(G1::THREADS);
+        if constexpr (G1::kPlanes) {
+            uint8_t* planes = reinterpret_cast<uint8_t*>((cx<T>*)ws + (size_t)jt.ntiles * ((size_t)kN1 * N2));
+            hipLaunchKernelGGL((k2_bits<N2>), dim3(jt.ntiles * (N2 / kBitsRows) * (kN1 / 64 / kBitsCols)), dim3(256), 0,
+                               (hipStream_t)stream, jt, planes);
+        }
         if constexpr (sizeof(T) == 4 && N2 == 2048) {
             static_assert(C1 == 8, "eight columns per workgroup");
-            hipLaunchKernelGGL((k2_pass1h<T>), grid, dim3(512), 0, (hipStream_t)stream, jt, (cx<T>*)ws, part,
+            hipLaunchKernelGGL((k2_pass1s<T>), dim3(2 * grid.x), dim3(512), 0, (hipStream_t)stream, jt, (cx<T>*)ws, part,
                                (const cx<T>*)tb.tw, (const cx<T>*)tb.stw, (const cx<double>*)tb.fa64,
                                (const cx<double>*)tb.fb64, tb.fshift);
         } else {

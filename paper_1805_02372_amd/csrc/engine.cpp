@@ -441,7 +441,7 @@ pa_status Lane::launch(Ctx* c, int prec_, int cls_, std::vector<JobDesc>& js, bo
     // tiles per launch: as many as the budget (and the lane cap) allows; on a
     // failed allocation halve until one tile
     const size_t elt = cfg.prec == 64 ? 16 : 8;
-    const size_t tile_bytes = (size_t)class_len(cfg.cls) * elt;
+    const size_t tile_bytes = (size_t)class_len(cfg.cls) * elt + cfg.ws_extra;
     const size_t part_bytes = (size_t)(cfg.n1 / cfg.b1) * sizeof(uint32_t);
     size_t G = total;
     if (ws.fixed) {   // a fixed workspace: as many tiles as it holds
@@ -556,7 +556,10 @@ pa_status Lane::finish(Ctx* c, uint32_t flags, pa_stats* stats, std::vector<pa_s
     pa_status st = lane_tables(c, *this, PREC_FP64, cls, &tb);
     if (st == PA_OK) st = lane_tables(c, *this, PREC_FP32, cls, &tb32);
     if (st != PA_OK) return st;
-    st = ws.ensure(c, (size_t)class_len(cls) * 16, stream);
+    // the FP64 tile, or the FP32 tile with its bit planes
+    st = ws.ensure(c, std::max<size_t>((size_t)class_len(cls) * 16,
+                                       (size_t)class_len(cls) * 8 + (K32 ? K32->cfg.ws_extra : 0)),
+                   stream);
     if (st != PA_OK) return st;
     const size_t part_words = std::max<size_t>(K64->cfg.n1 / K64->cfg.b1, K32 ? K32->cfg.n1 / K32->cfg.b1 : 0);
     st = part.ensure(c, part_words * sizeof(uint32_t), stream);

@@ -4,8 +4,9 @@
 // one file-scope device array, `scratch`, of fixed size (each GPU that the
 // library runs on holds its own copy until the process ends):
 //
-//   [0, 128 MiB)            tile workspace (pass 1 -> 2 -> 3), or the
-//                           reversed key of the direct product
+//   [0, 132 MiB)            tile workspace (pass 1 -> 2 -> 3: two FP32 tiles
+//                           of 2^23 points with their 2 MiB bit planes), or
+//                           the reversed key of the direct product
 //   + 512 KiB               per-tile partial key weights (pass 1 -> 2)
 //   + 256 KiB               per-tile certificates (at most 16384 tiles)
 //   + 8 x 512 KiB           twiddle tables of up to 8 length classes
@@ -25,7 +26,7 @@
 #include "engine.hpp"
 
 namespace {
-constexpr size_t kWsBytes = 128ull << 20;
+constexpr size_t kWsBytes = 132ull << 20;
 constexpr size_t kPartBytes = 512ull << 10;
 constexpr size_t kMetaBytes = 256ull << 10;
 constexpr size_t kTabSlotBytes = 512ull << 10;

@@ -75,6 +75,7 @@ struct ClassCfg {
     int n1, n2;           // row length (pass 2), column length (pass 1/3)
     int b1, b3;           // columns per workgroup in pass 1 / pass 3
     int r;                // points per thread
+    size_t ws_extra = 0;  // workspace bytes per tile beyond its points (pass 1's bit planes)
 };
 
 // Device pointers of a class's twiddle tables (element type matches prec).
