@@ -129,13 +129,26 @@ template <int A, int B> constexpr int cmax() { return A > B ? A : B; }
 
 // ------------------------------------------------------------------ pass 1
 // NT2: length of the root table tw of the column transforms (a multiple of N2).
+// FP64 column passes take the split exchange where their complex buffer
+// would leave room for one workgroup per compute unit, and their registers
+// are budgeted for two workgroups (the mixed-radix columns of 1280 to 1792
+// points, no spills).  FP32 column workgroups of eight and more waves then
+// get 128 registers or fewer and spill: measured slower.
+template <typename T, int N, int F> constexpr bool column_split() {
+    return split_exchange<T, N, F>() && sizeof(T) == 8;
+}
+template <typename T, int N, int F, int THREADS> constexpr int column_waves_per_eu() {
+    return column_split<T, N, F>() ? (2 * THREADS / 64 + 3) / 4 : 1;
+}
 template <typename T, int N1, int N2, int B, int R, int NT2>
 __global__ void __launch_bounds__(B * (N2 / R))
+__attribute__((amdgpu_waves_per_eu(column_waves_per_eu<T, N2, B, B * (N2 / R)>())))
 k_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part,
         const cx<T>* __restrict__ tw, const cx<T>* __restrict__ fa, const cx<T>* __restrict__ fb, int fshift) {
     constexpr uint32_t L = (uint32_t)N1 * N2;
     constexpr int NCB = N1 / B, NR = N2 / R, NT = NT2;
-    __shared__ cx<T> lds[lds_slots<N2, B>()];
+    constexpr bool SPLIT = column_split<T, N2, B>();
+    __shared__ cx<T> lds[SPLIT ? (lds_slots<N2, B>() + 1) / 2 : lds_slots<N2, B>()];
     __shared__ uint32_t wsum;
 
     const uint32_t lt = blockIdx.x / NCB;          // tile within this launch
@@ -152,7 +165,7 @@ k_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part,
     // fields at positions cb B + N1 t2 .. + B - 1 (key bits low, seed bits
     // high), read as funnel-shifted words instead of one load per point.  The
     // FFT's first barrier precedes its first LDS write.
-    static_assert(B <= 8 && 2 * N2 <= lds_slots<N2, B>() * (int)sizeof(cx<T>), "bit fields");
+    static_assert(B <= 8 && 2 * N2 <= lds_slots<N2, B>() * (int)sizeof(T), "bit fields");
     constexpr int NTH = B * (N2 / R);
     uint16_t* fld = reinterpret_cast<uint16_t*>(lds);
     const uint32_t bi = (uint32_t)g.bi, win = (uint32_t)(g.bi + g.bo - 1);
@@ -178,7 +191,7 @@ k_pass1(JobTable jt, cx<T>* __restrict__ ws, uint32_t* __restrict__ part,
     }
     atomicAdd(&wsum, pc);
 
-    fft<T, -1, N2, R, B, NT>(v, lds, j, f, tw);
+    fft<T, -1, N2, R, B, NT, SPLIT>(v, lds, j, f, tw);
 
     cx<T>* __restrict__ Y = ws + (size_t)lt * L;
 #pragma unroll
@@ -317,11 +330,13 @@ template <> __device__ __forceinline__ double round_even<double>(double z) { ret
 // row 0 as re / im.
 template <typename T, int N1, int N2, int B, int R, int NT2, bool SPLIT = false>
 __global__ void __launch_bounds__(B * (N2 / 2 / R))
+__attribute__((amdgpu_waves_per_eu(column_waves_per_eu<T, N2 / 2, B, B * (N2 / 2 / R)>())))
 k_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta, const cx<T>* __restrict__ tw) {
     constexpr uint32_t L = (uint32_t)N1 * N2;
     constexpr int N2h = N2 / 2, NR = N2h / R, NCB = N1 / B, NT = NT2;
     static_assert(64 % B == 0, "column groups must tile a wavefront");
-    __shared__ cx<T> lds[lds_slots<N2h, B>()];
+    constexpr bool XSPLIT = column_split<T, N2h, B>();
+    __shared__ cx<T> lds[XSPLIT ? (lds_slots<N2h, B>() + 1) / 2 : lds_slots<N2h, B>()];
     __shared__ uint32_t s_res, s_abs, s_bad;
 
     const uint32_t lt = blockIdx.x / NCB;
@@ -342,29 +357,34 @@ k_pass3(JobTable jt, const cx<T>* __restrict__ ws, TileMeta* __restrict__ meta, 
     // E = H[k] + conj H[n2/2-k], O = (H[k] - conj H[n2/2-k]) w_n2^{-k}.
     constexpr int NTH = B * (N2h / R);
     __shared__ T hrow[B];
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const int x = tid + q * NTH, k = x / B, c = x % B;
-        lds[lds_slot<B>(k, c)] = V[(size_t)k * N1 + cb * B + c];
-    }
     if (tid < B) hrow[tid] = SPLIT ? V[(size_t)N2h * N1 + cb * B + tid].re : V[cb * B + tid].im;
+    // XSPLIT: each thread reads both rows of its pairs from global memory
+    // (B-element row segments; the second read of a row comes from the L2),
+    // so that the LDS holds only the exchanges of the transform
+    if constexpr (!XSPLIT) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int x = tid + q * NTH, k = x / B, c = x % B;
+            lds[lds_slot<B>(k, c)] = V[(size_t)k * N1 + cb * B + c];
+        }
+    }
     __syncthreads();
     cx<T> v[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const int k = j + i * NR;
-        const cx<T> h = lds[lds_slot<B>(k, f)];
+        const cx<T> h = XSPLIT ? V[(size_t)k * N1 + t1] : lds[lds_slot<B>(k, f)];
         if (k == 0) {
             const T hh = hrow[f];   // H[n2/2]
             v[i] = cx<T>{h.re + hh, h.re - hh};
         } else {
-            const cx<T> hm = conj(lds[lds_slot<B>(N2h - k, f)]);
+            const cx<T> hm = conj(XSPLIT ? V[(size_t)(N2h - k) * N1 + t1] : lds[lds_slot<B>(N2h - k, f)]);
             const cx<T> e = h + hm;
             const cx<T> o = cmulc(h - hm, tw[k * (NT / N2)]);
             v[i] = cx<T>{e.re - o.im, e.im + o.re};
         }
     }
-    fft<T, +1, N2h, R, B, NT>(v, lds, j, f, tw);
+    fft<T, +1, N2h, R, B, NT, XSPLIT>(v, lds, j, f, tw);
 
     float mres = 0.f, mabs = 0.f;
     uint32_t bad = 0;

@@ -239,7 +239,11 @@ constexpr bool stockham_ok(int N, int R) {
 
 // One Stockham stage.  v: the thread's R points (layout described above).
 // tw: forward roots of unity w_NT^e at tw[e]; NT a multiple of N.
-template <typename T, int DIR, int N, int R, int Rs, int Ns, int F, int NT>
+// SPLIT: the exchange moves the real parts, then the imaginary parts, through
+// an LDS buffer of lds_slots<N, F>() scalars (half the bytes, two more
+// barriers per stage), for transforms whose complex buffer would leave room
+// for only one workgroup per compute unit.
+template <typename T, int DIR, int N, int R, int Rs, int Ns, int F, int NT, bool SPLIT>
 __device__ __forceinline__ void stockham_stage(cx<T> (&v)[R], cx<T>* lds, int j, int f,
                                                const cx<T>* __restrict__ tw) {
     constexpr int P = R / Rs;
@@ -261,7 +265,7 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[R], cx<T>* lds, int j,
 #pragma unroll
         for (int r = 0; r < Rs; ++r) v[p + r * P] = u[r];
     }
-    if constexpr (!LAST) {
+    if constexpr (!LAST && !SPLIT) {
         __syncthreads();  // everyone has finished reading the previous exchange
 #pragma unroll
         for (int p = 0; p < P; ++p) {
@@ -274,27 +278,58 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[R], cx<T>* lds, int j,
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < R; ++i) v[i] = lds[lds_slot<F>(j + i * NR, f)];
+    } else if constexpr (!LAST) {
+        // the real parts, then the imaginary parts: the writes of a half read
+        // the parts of v that its reads have not replaced yet
+        T* __restrict__ half = reinterpret_cast<T*>(lds);
+#pragma unroll
+        for (int part = 0; part < 2; ++part) {
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int q = j + p * NR;
+                const int k = q % Ns;
+                const int base = (q / Ns) * Ns * Rs + k;
+#pragma unroll
+                for (int r = 0; r < Rs; ++r)
+                    half[lds_slot<F>(base + r * Ns, f)] = part ? v[p + r * P].im : v[p + r * P].re;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const T x = half[lds_slot<F>(j + i * NR, f)];
+                if (part) v[i].im = x;
+                else v[i].re = x;
+            }
+        }
     }
 }
 
-template <typename T, int DIR, int N, int R, int F, int NT, int Ns>
+template <typename T, int DIR, int N, int R, int F, int NT, int Ns, bool SPLIT>
 __device__ __forceinline__ void fft_stages(cx<T> (&v)[R], cx<T>* lds, int j, int f,
                                            const cx<T>* __restrict__ tw) {
     constexpr int Rs = stockham_radix(N, R, Ns);
     static_assert(R % Rs == 0, "stage radix divides the points per thread");
-    stockham_stage<T, DIR, N, R, Rs, Ns, F, NT>(v, lds, j, f, tw);
-    if constexpr (Ns * Rs < N) fft_stages<T, DIR, N, R, F, NT, Ns * Rs>(v, lds, j, f, tw);
+    stockham_stage<T, DIR, N, R, Rs, Ns, F, NT, SPLIT>(v, lds, j, f, tw);
+    if constexpr (Ns * Rs < N) fft_stages<T, DIR, N, R, F, NT, Ns * Rs, SPLIT>(v, lds, j, f, tw);
 }
 
 // N-point FFT of F interleaved transforms held by N/R * F threads.  On entry
 // register i of thread (f, j) holds x_f[j + i N/R]; on exit X_f[j + i N/R].
-// The LDS buffer must hold lds_slots<N, F>() elements.  Contains barriers:
-// every thread of the workgroup must call it.
-template <typename T, int DIR, int N, int R, int F, int NT>
+// The LDS buffer must hold lds_slots<N, F>() elements (SPLIT: that many
+// scalars).  Contains barriers: every thread of the workgroup must call it.
+template <typename T, int DIR, int N, int R, int F, int NT, bool SPLIT = false>
 __device__ __forceinline__ void fft(cx<T> (&v)[R], cx<T>* lds, int j, int f,
                                     const cx<T>* __restrict__ tw) {
     static_assert(stockham_ok(N, R), "N = P 2^k (P = 1, 3, 5, 7), R a multiple of P and of 2");
-    fft_stages<T, DIR, N, R, F, NT, 1>(v, lds, j, f, tw);
+    fft_stages<T, DIR, N, R, F, NT, 1, SPLIT>(v, lds, j, f, tw);
+}
+
+// Whether a workgroup's complex exchange buffer of N F points would leave
+// room for only one workgroup per compute unit (160 KB of LDS), so that the
+// split exchange lets two share it.
+template <typename T, int N, int F> constexpr bool split_exchange() {
+    return (size_t)lds_slots<N, F>() * sizeof(cx<T>) > 81920;
 }
 
 }  // namespace pa
