@@ -99,3 +99,25 @@ def test_configs_take_mixed_radix_tiles(pa, ctx, monkeypatch):
         assert s["fft_len"] == want and s["tiles"] == 1, s
         digest = hashlib.sha256(np.ascontiguousarray(y, dtype="<u8").tobytes()).hexdigest()
         assert digest == golden[name]["sha256"], name
+
+
+@pytest.mark.parametrize("L", [3 << 22, 5 << 21, 7 << 21])
+def test_mixed_radix_fallback_accumulated(pa, ctx, L, monkeypatch):
+    """All-ones key and seed in the mixed-radix classes whose FP64 column
+    passes exchange real and imaginary parts in turn (n2 = 1536, 1280, 1792).
+    Every key chunk weighs more than 2^20, so every FP32 tile fails its
+    certificate and is re-run in FP64 with the key chunks XOR-accumulated
+    (Eq. 4-7).  Closed form: every output is the parity of n."""
+    from gpu_util import gpu_hash
+    monkeypatch.setenv("PA_ONLY_LEN", str(L))
+    n, m = L * 3 // 2 + 1, 1_000_003
+    seed = synth.pattern_bits("ones", n + m - 1)
+    key = synth.pattern_bits("ones", n)
+    plan = pa.pa_plan_query(n, m, pa.PA_PREC_FP32_SEG)
+    assert plan["fft_len"] == L and plan["chunks"] > 1, plan
+    print(f"L={L} n={n} m={m} plan {plan['chunks']}x{plan['windows']}", flush=True)
+    st, y = gpu_hash(pa, ctx, seed, n, m, key, pa.PA_PREC_FP32_SEG)
+    assert st == pa.PA_OK, pa.pa_strerror(st)
+    s = pa.pa_last_stats(ctx)
+    assert s["fallback_tiles"] >= plan["chunks"] * plan["windows"], s
+    assert np.array_equal(synth.bits_to_array(y, m), np.full(m, n & 1, np.uint8)), s
